@@ -1,0 +1,163 @@
+/*
+ * evlbm.h -- C ABI of the MI355X (gfx950) Enskog-Vlasov lattice Boltzmann
+ * library.  It implements the explicit lattice Boltzmann model of
+ * Karlin & Hosseini, "Practical Kinetic Models for Dense Fluids"
+ * (arXiv 2508.00577): the update eq. pre_LBM with the half-step fields of
+ * eq. u_shift / T_shift, the Enskog-gauge force of eq. EVforce1 under
+ * eq. P0E, the product equilibria eq. feq / f_star / geq / gstar with the
+ * corrections eq. correction_u / correction_gamma / correction_q, on the
+ * D3Q27 velocity set (text before eq. phi) and its z-summed D2Q9 form.
+ *
+ * Conventions
+ *   - Every call returns an int: EVLBM_OK (0) or a negative error code;
+ *     evlbm_last_error() gives a message for the calling thread.
+ *   - Lattice units: dt = dx = 1, particle mass 1 (rho = n).
+ *   - Fields are SoA with x fastest: scalar[nz][ny][nx], vector[D][nz][ny][nx],
+ *     populations [Q][nz][ny][nx] (f) followed by the same for g.
+ *     Velocity index i = (cx+1) + 3 (cy+1) + 9 (cz+1) on D3Q27 and
+ *     i = (cx+1) + 3 (cy+1) on D2Q9, c in {-1,0,1}.
+ *   - `where` selects host FP64 arrays or device arrays (FP32/FP64) on the
+ *     handle's device; the caller owns every buffer it passes and keeps it
+ *     alive for the duration of the call.  Host reads block until the data
+ *     is on the host; everything else is enqueued on the handle's stream.
+ *   - A handle is not thread-safe; separate handles are independent.
+ *   - The periodic lattice is the only boundary condition.
+ */
+#ifndef EVLBM_H
+#define EVLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    EVLBM_OK = 0,
+    EVLBM_EINVAL = -1,      /* invalid argument */
+    EVLBM_ENOMEM = -2,      /* device or host allocation failed */
+    EVLBM_EHIP = -3,        /* a HIP runtime call failed */
+    EVLBM_ESTATE = -4,      /* call not valid in the handle's state */
+    EVLBM_ENONFINITE = -5,  /* a non-finite density was found */
+    EVLBM_EIO = -6,         /* file I/O failed */
+    EVLBM_ENONPHYS = -7     /* rho <= 0, b rho >= 1 or T <= 0 in an input */
+};
+
+enum { EVLBM_D2Q9 = 2, EVLBM_D3Q27 = 3 };
+
+/* Population storage.  F16DEV/BF16DEV store h_i = f_i - f_i^ref in 16 bits,
+ * f^ref the equilibrium of a uniform reference state at rest (options
+ * EVLBM_OPT_REF_RHO, EVLBM_OPT_REF_T), decoded to FP32 for the arithmetic. */
+enum { EVLBM_F64 = 0, EVLBM_F32 = 1, EVLBM_F16DEV = 2, EVLBM_BF16DEV = 3 };
+
+enum { EVLBM_HOST_F64 = 0, EVLBM_DEVICE_F32 = 1, EVLBM_DEVICE_F64 = 2 };
+
+enum {
+    EVLBM_OPT_SPHI = 1,        /* sign in front of the first term of eq. correction_u (default -1) */
+    EVLBM_OPT_REF_RHO = 2,     /* reference density of the 16-bit deviation storage */
+    EVLBM_OPT_REF_T = 3,       /* reference temperature of the 16-bit deviation storage */
+    EVLBM_OPT_CHECK_EVERY = 4, /* scan for non-finite densities every K steps (0 = never) */
+    EVLBM_OPT_USE_GRAPH = 5    /* 1: replay step chunks from a captured hipGraph (default 1) */
+};
+
+enum { EVLBM_MEASURE_SLAB = 1, EVLBM_MEASURE_DROPLET = 2 };
+
+typedef struct evlbm_lattice *evlbm_t;
+
+/* Message of the last failed call on this thread (never NULL). */
+const char *evlbm_last_error(void);
+
+/* Create a periodic lattice of nx*ny*nz cells (D2Q9 needs nz == 1) with the
+ * given storage, bound to `stream` (a hipStream_t; NULL = default stream) on
+ * the current device.  Allocates two population buffers (2*2Q*N values) and a
+ * moment field.  Parameters start at R = 1, a = b = kappa = 0, tau = lambda = 1.
+ * Errors: EINVAL (unknown lattice or storage, sizes <= 0, nz != 1 for D2Q9),
+ * ENOMEM, EHIP. */
+int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream, evlbm_t *out);
+
+/* Release every resource of the handle; NULL is accepted. */
+int evlbm_destroy(evlbm_t h);
+
+/* Equation of state: Enskog pressure P_E = rho R T/(1 - b rho), mean-field
+ * pressure P_V = -a rho^2 and capillarity kappa (eq. EVforce1 and the text
+ * after it).  a = b = kappa = 0 is the ideal gas.
+ * Errors: EINVAL if R <= 0 or a, b, kappa < 0. */
+int evlbm_set_eos(evlbm_t h, double R, double a, double b, double kappa);
+
+/* Relaxation: bare time tau (beta = dt/(2 tau + dt), eq. beta) and the shifted-
+ * equilibrium time lambda.  Errors: EINVAL if tau <= 0, lambda <= 0 or
+ * tau > lambda (negative effective relaxation time, eq. final_kinetic_model2). */
+int evlbm_set_relaxation(evlbm_t h, double tau, double lambda);
+
+/* Set an EVLBM_OPT_* option.  Errors: EINVAL (unknown key or bad value). */
+int evlbm_set_option(evlbm_t h, int key, double value);
+
+/* Initialise f = f^eq(rho, u, P0/rho) and g = g^eq(u, RT) cell by cell from
+ * rho[N], u[D*N] (may be NULL: at rest) and T[N]; resets the step count.
+ * Errors: EINVAL (bad where), ENONPHYS (rho <= 0, b rho >= 1 or T <= 0),
+ * ENONFINITE, EHIP. */
+int evlbm_init_fields(evlbm_t h, const void *rho, const void *u, const void *T, int where);
+
+/* Advance nsteps time steps on the handle's stream (asynchronous unless the
+ * non-finite scan is enabled).  Errors: ESTATE (not initialised), ENONFINITE
+ * (scan), EHIP. */
+int evlbm_step(evlbm_t h, int64_t nsteps);
+
+/* Steps taken since the last initialisation. */
+int evlbm_step_count(evlbm_t h, int64_t *out);
+
+/* Moments of the current state (pull, raw moments, force and half-step
+ * fields, eq. u_shift and eq. T_shift): rho[N], u[D*N], T[N] (any may be
+ * NULL).  Errors: ESTATE, EINVAL, EHIP. */
+int evlbm_read_moments(evlbm_t h, void *rho, void *u, void *T, int where);
+
+/* FP64 global sums of the current state: out[0] = sum rho, out[1..3] =
+ * sum rho u, out[4] = sum rho E, out[5] = sum [rho E - a rho^2 +
+ * (kappa/2)|grad rho|^2], out[6] = max |u|, out[7] = min of the streamed f.
+ * Blocks.  Errors: ESTATE, EHIP. */
+int evlbm_global_sums(evlbm_t h, double out[8]);
+
+/* FP64 region means for the coexistence (Fig. 1) and Laplace checks.
+ * SLAB: geom = {xl0, xl1, xv0, xv1, xv2, xv3}: liquid x in [xl0, xl1),
+ *   vapour x in [xv0, xv1) U [xv2, xv3) (all y, z).
+ * DROPLET: geom = {cx, cy, cz, r_in, r_out}: inside r < r_in, outside r > r_out.
+ * out = {rho_in, rho_out, T_in, T_out, P_in, P_out, R_e, cells_in}
+ * with P = rho R T/(1 - b rho) - a rho^2 and, for droplets, the equimolar
+ * radius R_e from sum (rho - rho_out)/(rho_in - rho_out) (2D: area, 3D:
+ * volume).  Blocks.  Errors: EINVAL, ESTATE, EHIP. */
+int evlbm_measure(evlbm_t h, int kind, const double *geom, double out[8]);
+
+/* Copy the stored populations out (decoded) or in (encoded): f[Q*N], g[Q*N]
+ * in the library layout.  Errors: EINVAL, EHIP. */
+int evlbm_get_populations(evlbm_t h, void *f, void *g, int where);
+int evlbm_set_populations(evlbm_t h, const void *f, const void *g, int where);
+
+/* Bit-exact dump of the stored populations with a text header (lattice,
+ * storage, sizes, parameters, step); load restores them into a handle of
+ * the same lattice, sizes and storage.  Errors: EIO, EINVAL. */
+int evlbm_checkpoint_save(evlbm_t h, const char *path);
+int evlbm_checkpoint_load(evlbm_t h, const char *path);
+
+/* Time the two kernels of a step with HIP events on the handle's stream:
+ * runs nsteps real steps (launched one by one, no graph) and returns the
+ * average durations in milliseconds: out[0] = pulled-moment kernel,
+ * out[1] = stencil + collision kernel.  Blocks.
+ * Errors: EINVAL (nsteps outside 1..4096), ESTATE, EHIP. */
+int evlbm_profile_step(evlbm_t h, int nsteps, double out[2]);
+
+/* Wait for all work enqueued on the handle's stream. */
+int evlbm_synchronize(evlbm_t h);
+
+/* van der Waals coexistence at temperature T: out = {rho_l, rho_v, P_coex}
+ * (equal pressure and chemical potential, Newton iteration).  Used for the
+ * initial profiles.  Errors: EINVAL if T is not below T_c = 8a/(27 b R). */
+int evlbm_eos_coexistence(double R, double a, double b, double T, double out[3]);
+
+/* Build information: "gfx950 <storage variants> <date>" (static string). */
+const char *evlbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EVLBM_H */

@@ -1,0 +1,234 @@
+"""Python binding of libevlbm, the MI355X (gfx950) Enskog-Vlasov lattice Boltzmann library.
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch provides device memory (output tensors) and streams.  The
+names follow include/evlbm.h; errors raise EvlbmError with the library's
+message.  The library must have been built (``python -m
+paper_2508_00577_amd.build`` or ``__graft_entry__.build()``); nothing here
+falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libevlbm.so")
+
+D2Q9, D3Q27 = 2, 3
+F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
+HOST_F64, DEVICE_F32, DEVICE_F64 = 0, 1, 2
+OPT_SPHI, OPT_REF_RHO, OPT_REF_T, OPT_CHECK_EVERY, OPT_USE_GRAPH = 1, 2, 3, 4, 5
+MEASURE_SLAB, MEASURE_DROPLET = 1, 2
+STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE", -6: "EIO", -7: "ENONPHYS"}
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class EvlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+_lib = None
+
+
+def lib():
+    """Load libevlbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        # torch ships its own HIP runtime; load it first so that this library
+        # binds to the same runtime (one HIP runtime per process)
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2508_00577_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.evlbm_last_error.restype = ctypes.c_char_p
+        L.evlbm_version.restype = ctypes.c_char_p
+        L.evlbm_create.argtypes = [ctypes.c_int] * 5 + [_vp, ctypes.POINTER(_vp)]
+        L.evlbm_destroy.argtypes = [_vp]
+        L.evlbm_set_eos.argtypes = [_vp] + [ctypes.c_double] * 4
+        L.evlbm_set_relaxation.argtypes = [_vp, ctypes.c_double, ctypes.c_double]
+        L.evlbm_set_option.argtypes = [_vp, ctypes.c_int, ctypes.c_double]
+        L.evlbm_init_fields.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int]
+        L.evlbm_step.argtypes = [_vp, ctypes.c_int64]
+        L.evlbm_step_count.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
+        L.evlbm_read_moments.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int]
+        L.evlbm_global_sums.argtypes = [_vp, _dp]
+        L.evlbm_measure.argtypes = [_vp, ctypes.c_int, _dp, _dp]
+        L.evlbm_get_populations.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+        L.evlbm_set_populations.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+        L.evlbm_checkpoint_save.argtypes = [_vp, ctypes.c_char_p]
+        L.evlbm_checkpoint_load.argtypes = [_vp, ctypes.c_char_p]
+        L.evlbm_synchronize.argtypes = [_vp]
+        L.evlbm_profile_step.argtypes = [_vp, ctypes.c_int, _dp]
+        L.evlbm_eos_coexistence.argtypes = [ctypes.c_double] * 4 + [_dp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise EvlbmError(rc, lib().evlbm_last_error().decode())
+
+
+def _host(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(_vp)
+    return ctypes.c_void_p(a.data_ptr())  # torch tensor
+
+
+def eos_coexistence(T, R=1.0, a=0.0225, b=1.0 / 3.0):
+    """(rho_l, rho_v, P_coex) of the van der Waals equation at temperature T."""
+    out = np.zeros(3)
+    _check(lib().evlbm_eos_coexistence(R, a, b, T, out.ctypes.data_as(_dp)))
+    return tuple(out)
+
+
+def version():
+    return lib().evlbm_version().decode()
+
+
+class Lattice:
+    """One periodic lattice on the GPU: D2Q9 (nz = 1) or D3Q27.
+
+    Fields are indexed [nz, ny, nx] (x fastest); vectors [D, nz, ny, nx].
+    `storage` is one of 'f64', 'f32', 'f16dev', 'bf16dev'.  A dedicated torch
+    stream is used unless one is given.
+    """
+
+    def __init__(self, D, nx, ny, nz=1, storage="f32", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a visible GPU")
+        self.D, self.nx, self.ny, self.nz = D, nx, ny, nz
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self.Q = 9 if D == 2 else 27
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = _vp()
+        _check(lib().evlbm_create(D, nx, ny, nz, self.storage, _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.evlbm_destroy(h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    # -- parameters
+    def set_eos(self, R=1.0, a=0.0, b=0.0, kappa=0.0):
+        _check(lib().evlbm_set_eos(self._h, R, a, b, kappa))
+
+    def set_relaxation(self, tau=1.0, lam=1.0):
+        _check(lib().evlbm_set_relaxation(self._h, tau, lam))
+
+    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0):
+        self.set_eos(R, a, b, kappa)
+        self.set_relaxation(tau, lam)
+        self.set_option(OPT_SPHI, sphi)
+
+    def set_option(self, key, value):
+        _check(lib().evlbm_set_option(self._h, int(key), float(value)))
+
+    # -- state
+    def init_fields(self, rho, T, u=None):
+        """Initialise from host (numpy, FP64) or device (torch, FP32/FP64) fields."""
+        if isinstance(rho, np.ndarray):
+            rho, T = _host(rho), _host(T)
+            u = None if u is None else _host(u)
+            where = HOST_F64
+        else:
+            import torch
+            where = DEVICE_F64 if rho.dtype == torch.float64 else DEVICE_F32
+            rho, T = rho.contiguous(), T.contiguous()
+            u = None if u is None else u.contiguous()
+        assert rho.size == self.N if isinstance(rho, np.ndarray) else rho.numel() == self.N
+        _check(lib().evlbm_init_fields(self._h, _ptr(rho), _ptr(u), _ptr(T), where))
+
+    def step(self, n=1):
+        _check(lib().evlbm_step(self._h, int(n)))
+
+    @property
+    def step_count(self):
+        v = ctypes.c_int64()
+        _check(lib().evlbm_step_count(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def synchronize(self):
+        _check(lib().evlbm_synchronize(self._h))
+
+    def profile_step(self, nsteps=20):
+        """Average kernel durations (ms) of (moments, collide) over nsteps real steps."""
+        out = np.zeros(2)
+        _check(lib().evlbm_profile_step(self._h, int(nsteps), out.ctypes.data_as(_dp)))
+        return float(out[0]), float(out[1])
+
+    def moments(self, device=False, dtype=None):
+        """(rho, u, T) of the current state: numpy FP64 (default) or torch tensors."""
+        if not device:
+            rho = np.zeros(self.shape)
+            u = np.zeros((self.D,) + self.shape)
+            T = np.zeros(self.shape)
+            _check(lib().evlbm_read_moments(self._h, _ptr(rho), _ptr(u), _ptr(T), HOST_F64))
+            return rho, u, T
+        import torch
+        dtype = dtype or torch.float32
+        with torch.cuda.stream(self.stream):
+            rho = torch.empty(self.shape, dtype=dtype, device="cuda")
+            u = torch.empty((self.D,) + self.shape, dtype=dtype, device="cuda")
+            T = torch.empty(self.shape, dtype=dtype, device="cuda")
+        where = DEVICE_F64 if dtype == torch.float64 else DEVICE_F32
+        _check(lib().evlbm_read_moments(self._h, _ptr(rho), _ptr(u), _ptr(T), where))
+        return rho, u, T
+
+    def global_sums(self):
+        out = np.zeros(8)
+        _check(lib().evlbm_global_sums(self._h, out.ctypes.data_as(_dp)))
+        return out
+
+    def measure_slab(self, liquid, vapour1, vapour2):
+        g = np.array([liquid[0], liquid[1], vapour1[0], vapour1[1], vapour2[0], vapour2[1]], dtype=np.float64)
+        out = np.zeros(8)
+        _check(lib().evlbm_measure(self._h, MEASURE_SLAB, g.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
+        return out
+
+    def measure_droplet(self, centre, r_in, r_out):
+        c = list(centre) + [0.0] * (3 - len(centre))
+        g = np.array(c + [r_in, r_out, 0.0], dtype=np.float64)
+        out = np.zeros(8)
+        _check(lib().evlbm_measure(self._h, MEASURE_DROPLET, g.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
+        return out
+
+    def get_populations(self):
+        f = np.zeros((self.Q,) + self.shape)
+        g = np.zeros((self.Q,) + self.shape)
+        _check(lib().evlbm_get_populations(self._h, _ptr(f), _ptr(g), HOST_F64))
+        return f, g
+
+    def set_populations(self, f, g):
+        f, g = _host(f), _host(g)
+        assert f.size == self.Q * self.N and g.size == self.Q * self.N
+        _check(lib().evlbm_set_populations(self._h, _ptr(f), _ptr(g), HOST_F64))
+
+    def checkpoint_save(self, path):
+        _check(lib().evlbm_checkpoint_save(self._h, str(path).encode()))
+
+    def checkpoint_load(self, path):
+        _check(lib().evlbm_checkpoint_load(self._h, str(path).encode()))

@@ -1,0 +1,45 @@
+// Library-internal state shared by the lattice, batch and network sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "evlbm.h"
+
+struct evlbm_lattice {
+    int D = 2, Q = 9, nx = 0, ny = 0, nz = 0, storage = EVLBM_F32;
+    long N = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    void *buf[2] = {nullptr, nullptr};  // population buffers, f then g, [2Q][N]
+    int cur = 0;                        // buffer holding the current state
+    void *m = nullptr;                  // pulled moments rho, j (D), e: [(D+2)][N]
+    void *lap = nullptr;                // readout scratch: lap rho [N]
+    void *scratch = nullptr;            // I/O and reduction scratch
+    size_t scratch_bytes = 0;
+    // model
+    double R = 1.0, a = 0.0, b = 0.0, kappa = 0.0, tau = 1.0, lambda = 1.0, sphi = -1.0;
+    double ref_rho = 1.0, ref_T = 0.02;  // deviation-storage reference state
+    int64_t check_every = 0;
+    bool use_graph = true;
+    // state
+    int64_t step = 0;
+    bool initialized = false;
+    bool m_valid = false;
+    hipGraphExec_t graph_exec_par[2] = {nullptr, nullptr};  // captured step chunks, per buffer parity
+};
+
+namespace evlbm {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int ensure_scratch(evlbm_lattice *h, size_t bytes);
+void refresh_moments(evlbm_lattice *h);
+void launch_step(evlbm_lattice *h);
+int run_steps(evlbm_lattice *h, int64_t n);
+int scan_nonfinite(evlbm_lattice *h);
+size_t store_bytes(int storage);
+size_t real_bytes(int storage);
+void reference_populations(int D, double R, double b, double rho, double T, double out[54]);
+
+}  // namespace evlbm

@@ -1,0 +1,859 @@
+// C ABI of one periodic lattice (declared in include/evlbm.h): handle life
+// cycle, parameters, initialisation, time stepping, readout, reductions,
+// population I/O and checkpoints.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "evlbm_internal.hpp"
+#include "lbm_kernels.hpp"
+
+using namespace evlbm;
+
+namespace evlbm {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(EVLBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t store_bytes(int storage) { return storage == EVLBM_F64 ? 8 : storage == EVLBM_F32 ? 4 : 2; }
+size_t real_bytes(int storage) { return storage == EVLBM_F64 ? 8 : 4; }
+
+// Reference populations of the 16-bit deviation storage: the equilibrium of
+// a uniform state at rest with density ref_rho and temperature ref_T.
+void reference_populations(int D, double R, double b, double rho, double T, double out[54])
+{
+    const int Q = D == 2 ? 9 : 27;
+    const double RT = R * T;
+    const double theta = RT / (1.0 - b * rho);
+    double fe[3][3], xe[3][3];
+    for (int a = 0; a < 3; ++a) {
+        // at rest: psi(0) = 1 - theta, psi(+-1) = theta/2; chi with u = 0:
+        // chi(0) = -theta^2, chi(+-1) = theta^2/2
+        if (a < D) {
+            fe[a][0] = fe[a][2] = 0.5 * theta;
+            fe[a][1] = 1.0 - theta;
+            xe[a][0] = xe[a][2] = 0.5 * theta * theta;
+            xe[a][1] = -theta * theta;
+        } else {
+            fe[a][0] = fe[a][2] = 0.0;
+            fe[a][1] = 1.0;
+            xe[a][0] = xe[a][1] = xe[a][2] = 0.0;
+        }
+    }
+    for (int i = 0; i < 54; ++i) out[i] = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = (D == 3 ? cz_of(i) : 0) + 1;
+        out[i] = rho * fe[0][kx] * fe[1][ky] * fe[2][kz];
+        out[Q + i] = rho * ((1.5 * RT * fe[0][kx] + xe[0][kx]) * fe[1][ky] * fe[2][kz] +
+                            fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
+    }
+}
+
+template <typename R>
+StepParams<R> make_params(const evlbm_lattice *h)
+{
+    StepParams<R> p;
+    p.nx = h->nx;
+    p.ny = h->ny;
+    p.nz = h->nz;
+    p.N = h->N;
+    p.a = (R)h->a;
+    p.b = (R)h->b;
+    p.kappa = (R)h->kappa;
+    const double beta = 1.0 / (2.0 * h->tau + 1.0);
+    p.two_beta = (R)(2.0 * beta);
+    p.wstar = (R)((1.0 / h->lambda) * (1.0 - beta));
+    p.lambda = (R)h->lambda;
+    p.sphi = (R)h->sphi;
+    p.Rgas = (R)h->R;
+    double ref[54];
+    if (h->storage == EVLBM_F16DEV || h->storage == EVLBM_BF16DEV)
+        reference_populations(h->D, h->R, h->b, h->ref_rho, h->ref_T, ref);
+    else
+        for (int i = 0; i < 54; ++i) ref[i] = 0.0;
+    for (int i = 0; i < 54; ++i) p.ref[i] = (R)ref[i];
+    return p;
+}
+
+template StepParams<float> make_params<float>(const evlbm_lattice *);
+template StepParams<double> make_params<double>(const evlbm_lattice *);
+
+static dim3 row_grid(const evlbm_lattice *h, int bx) { return dim3((h->nx + bx - 1) / bx, h->ny, h->nz); }
+static int row_block(const evlbm_lattice *h) { return h->nx >= 256 ? 256 : ((h->nx + 63) / 64) * 64; }
+
+// ------------------------------------------------------------- dispatch
+
+template <int D, int S>
+struct Ops {
+    using T = StoreT<S>;
+    using R = RealT<S>;
+    // tile of the collision kernel
+    static constexpr int BX = (D == 2) ? 64 : (S == EVLBM_F64 ? 16 : 32);
+    static constexpr int BY = 4;
+    static constexpr int BZ = (D == 2) ? 1 : 2;
+
+    static void moments(evlbm_lattice *h, const void *pop)
+    {
+        const int bx = row_block(h);
+        hipLaunchKernelGGL((k_moments<D, S>), row_grid(h, bx), dim3(bx), 0, h->stream, (const T *)pop, (R *)h->m,
+                           make_params<R>(h));
+    }
+    static void collide(evlbm_lattice *h, const void *src, void *dst)
+    {
+        dim3 grid((h->nx + BX - 1) / BX, (h->ny + BY - 1) / BY, (h->nz + BZ - 1) / BZ);
+        hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ>), grid, dim3(BX, BY, BZ), 0, h->stream, (const T *)src,
+                           (T *)dst, (const R *)h->m, make_params<R>(h));
+    }
+    static void init(evlbm_lattice *h, const double *rho, const double *u, const double *T0)
+    {
+        const long nb = (h->N + 255) / 256;
+        hipLaunchKernelGGL((k_init<D, S>), dim3(nb), dim3(256), 0, h->stream, rho, u, T0, (T *)h->buf[h->cur],
+                           make_params<R>(h));
+    }
+    static void lap(evlbm_lattice *h)
+    {
+        const int bx = row_block(h);
+        hipLaunchKernelGGL((k_lap_field<D, R>), row_grid(h, bx), dim3(bx), 0, h->stream, (const R *)h->m, (R *)h->lap,
+                           h->nx, h->ny, h->nz);
+    }
+    template <typename O>
+    static void readout(evlbm_lattice *h, O *rho, O *u, O *T0)
+    {
+        const int bx = row_block(h);
+        hipLaunchKernelGGL((k_readout<D, R, O>), row_grid(h, bx), dim3(bx), 0, h->stream, (const R *)h->m,
+                           (const R *)h->lap, rho, u, T0, h->nx, h->ny, h->nz, (R)h->a, (R)h->kappa, (R)h->R);
+    }
+    static void sums(evlbm_lattice *h, double *partial, long nb)
+    {
+        hipLaunchKernelGGL((k_sums<D, S>), dim3(nb), dim3(256), 0, h->stream, (const T *)h->buf[h->cur],
+                           (const R *)h->m, (const R *)h->lap, make_params<R>(h), partial);
+    }
+    static void measure(evlbm_lattice *h, int kind, const double *g, double *partial, long nb)
+    {
+        hipLaunchKernelGGL((k_measure<D, R>), dim3(nb), dim3(256), 0, h->stream, (const R *)h->m, (const R *)h->lap,
+                           h->nx, h->ny, h->nz, (R)h->a, (R)h->b, (R)h->kappa, (R)h->R, kind, g[0], g[1], g[2], g[3],
+                           g[4], g[5], partial);
+    }
+    static void decode(evlbm_lattice *h, double *out)
+    {
+        const long n = h->N * 2 * h->Q;
+        hipLaunchKernelGGL((k_decode<S>), dim3((n + 255) / 256), dim3(256), 0, h->stream, (const T *)h->buf[h->cur],
+                           out, h->N, 2 * h->Q, make_params<R>(h));
+    }
+    static void encode(evlbm_lattice *h, const double *in)
+    {
+        const long n = h->N * 2 * h->Q;
+        hipLaunchKernelGGL((k_encode<S>), dim3((n + 255) / 256), dim3(256), 0, h->stream, in, (T *)h->buf[h->cur],
+                           h->N, 2 * h->Q, make_params<R>(h));
+    }
+    static void scan(evlbm_lattice *h, int *flag)
+    {
+        hipLaunchKernelGGL((k_scan_nonfinite<R>), dim3((h->N + 255) / 256), dim3(256), 0, h->stream, (const R *)h->m,
+                           h->N, flag);
+    }
+};
+
+template <template <int, int> class F, typename... A>
+static void dispatch(evlbm_lattice *h, A &&...args)
+{
+#define EVLBM_CASE(DD, SS) \
+    if (h->D == DD && h->storage == SS) return F<DD, SS>::run(h, args...);
+    EVLBM_CASE(2, EVLBM_F64)
+    EVLBM_CASE(2, EVLBM_F32)
+    EVLBM_CASE(2, EVLBM_F16DEV)
+    EVLBM_CASE(2, EVLBM_BF16DEV)
+    EVLBM_CASE(3, EVLBM_F64)
+    EVLBM_CASE(3, EVLBM_F32)
+    EVLBM_CASE(3, EVLBM_F16DEV)
+    EVLBM_CASE(3, EVLBM_BF16DEV)
+#undef EVLBM_CASE
+}
+
+template <int D, int S>
+struct RunMoments {
+    static void run(evlbm_lattice *h, const void *pop) { Ops<D, S>::moments(h, pop); }
+};
+template <int D, int S>
+struct RunCollide {
+    static void run(evlbm_lattice *h, const void *src, void *dst) { Ops<D, S>::collide(h, src, dst); }
+};
+template <int D, int S>
+struct RunInit {
+    static void run(evlbm_lattice *h, const double *r, const double *u, const double *t) { Ops<D, S>::init(h, r, u, t); }
+};
+template <int D, int S>
+struct RunLap {
+    static void run(evlbm_lattice *h) { Ops<D, S>::lap(h); }
+};
+template <int D, int S>
+struct RunReadoutF {
+    static void run(evlbm_lattice *h, float *r, float *u, float *t) { Ops<D, S>::template readout<float>(h, r, u, t); }
+};
+template <int D, int S>
+struct RunReadoutD {
+    static void run(evlbm_lattice *h, double *r, double *u, double *t) { Ops<D, S>::template readout<double>(h, r, u, t); }
+};
+template <int D, int S>
+struct RunSums {
+    static void run(evlbm_lattice *h, double *p, long nb) { Ops<D, S>::sums(h, p, nb); }
+};
+template <int D, int S>
+struct RunMeasure {
+    static void run(evlbm_lattice *h, int kind, const double *g, double *p, long nb) { Ops<D, S>::measure(h, kind, g, p, nb); }
+};
+template <int D, int S>
+struct RunDecode {
+    static void run(evlbm_lattice *h, double *o) { Ops<D, S>::decode(h, o); }
+};
+template <int D, int S>
+struct RunEncode {
+    static void run(evlbm_lattice *h, const double *i) { Ops<D, S>::encode(h, i); }
+};
+template <int D, int S>
+struct RunScan {
+    static void run(evlbm_lattice *h, int *f) { Ops<D, S>::scan(h, f); }
+};
+
+// ------------------------------------------------------------- helpers
+
+int ensure_scratch(evlbm_lattice *h, size_t bytes)
+{
+    if (h->scratch_bytes >= bytes) return EVLBM_OK;
+    if (h->scratch) hipFree(h->scratch);
+    h->scratch = nullptr;
+    h->scratch_bytes = 0;
+    hipError_t e = hipMalloc(&h->scratch, bytes);
+    if (e != hipSuccess) return fail(EVLBM_ENOMEM, "hipMalloc(%zu) for scratch: %s", bytes, hipGetErrorString(e));
+    h->scratch_bytes = bytes;
+    return EVLBM_OK;
+}
+
+// Make sure h->m holds the pulled moments of the current buffer.
+void refresh_moments(evlbm_lattice *h)
+{
+    if (!h->m_valid) {
+        dispatch<RunMoments>(h, (const void *)h->buf[h->cur]);
+        h->m_valid = true;
+    }
+}
+
+static int check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return EVLBM_OK;
+}
+
+// Run the reduction with NV values per block through the partial buffer;
+// result copied to host out[NV].
+static int finish_reduce(evlbm_lattice *h, long nb, int nv, const int ops[8], double *out)
+{
+    double *partial = (double *)h->scratch;
+    double *res = partial + nb * nv;
+    int4 lo = make_int4(ops[0], ops[1], ops[2], ops[3]);
+    int4 hi = make_int4(ops[4], ops[5], ops[6], ops[7]);
+    if (nv == 8)
+        hipLaunchKernelGGL((k_reduce_final<8>), dim3(8), dim3(64), 0, h->stream, partial, nb, lo, hi, res);
+    else
+        hipLaunchKernelGGL((k_reduce_final<9>), dim3(8), dim3(64), 0, h->stream, partial, nb, lo, hi, res);
+    int rc = check_launch("reduce");
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(out, res, sizeof(double) * 8, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return EVLBM_OK;
+}
+
+int scan_nonfinite(evlbm_lattice *h)
+{
+    refresh_moments(h);
+    int rc = ensure_scratch(h, sizeof(int) * 64);
+    if (rc) return rc;
+    int *flag = (int *)h->scratch;
+    // clear with a copy (no memset node ever enters a captured graph here)
+    int zero = 0;
+    hipError_t e = hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    dispatch<RunScan>(h, flag);
+    int host = 0;
+    e = hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (host) return fail(EVLBM_ENONFINITE, "%d cells with a non-finite or non-positive density at step %lld", host,
+                          (long long)h->step);
+    return EVLBM_OK;
+}
+
+// One step: moments of the current buffer, collision into the other.
+void launch_step(evlbm_lattice *h)
+{
+    refresh_moments(h);
+    const int nxt = 1 - h->cur;
+    dispatch<RunCollide>(h, (const void *)h->buf[h->cur], h->buf[nxt]);
+    h->cur = nxt;
+    h->m_valid = false;
+    h->step++;
+}
+
+// Steps are replayed from a captured graph of GRAPH_STEPS launches pairs
+// (an even count, so the buffer parity is unchanged), one graph per parity.
+static constexpr int GRAPH_STEPS = 32;
+
+int run_steps(evlbm_lattice *h, int64_t n)
+{
+    const bool graph_ok = h->use_graph && h->stream != nullptr && n >= GRAPH_STEPS;
+    if (!graph_ok) {
+        for (int64_t k = 0; k < n; ++k) launch_step(h);
+        return EVLBM_OK;
+    }
+    const int par = h->cur;
+    if (!h->graph_exec_par[par]) {
+        const int cur0 = h->cur;
+        const int64_t step0 = h->step;
+        h->m_valid = false;
+        hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        for (int k = 0; k < GRAPH_STEPS; ++k) launch_step(h);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(h->stream, &g);
+        h->cur = cur0;
+        h->step = step0;
+        h->m_valid = false;
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        h->graph_exec_par[par] = ex;
+    }
+    const int64_t reps = n / GRAPH_STEPS;
+    for (int64_t r = 0; r < reps; ++r) {
+        hipError_t e = hipGraphLaunch(h->graph_exec_par[par], h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    }
+    h->step += reps * GRAPH_STEPS;
+    h->m_valid = false;
+    for (int64_t k = reps * GRAPH_STEPS; k < n; ++k) launch_step(h);
+    return EVLBM_OK;
+}
+
+}  // namespace evlbm
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char *evlbm_last_error(void) { return g_err; }
+
+const char *evlbm_version(void) { return "evlbm gfx950 D2Q9/D3Q27 F64/F32/F16DEV/BF16DEV"; }
+
+int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream, evlbm_t *out)
+{
+    if (!out) return fail(EVLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (lattice != EVLBM_D2Q9 && lattice != EVLBM_D3Q27) return fail(EVLBM_EINVAL, "unknown lattice %d", lattice);
+    if (storage < EVLBM_F64 || storage > EVLBM_BF16DEV) return fail(EVLBM_EINVAL, "unknown storage %d", storage);
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(EVLBM_EINVAL, "lattice sizes must be positive");
+    if (lattice == EVLBM_D2Q9 && nz != 1) return fail(EVLBM_EINVAL, "D2Q9 needs nz == 1");
+    evlbm_lattice *h = new evlbm_lattice();
+    h->D = lattice;
+    h->Q = lattice == EVLBM_D2Q9 ? 9 : 27;
+    h->nx = nx;
+    h->ny = ny;
+    h->nz = nz;
+    h->N = (long)nx * ny * nz;
+    h->storage = storage;
+    h->stream = (hipStream_t)stream;
+    hipGetDevice(&h->device);
+    const size_t pop_bytes = (size_t)h->N * 2 * h->Q * store_bytes(storage);
+    const size_t m_bytes = (size_t)h->N * (h->D + 2) * real_bytes(storage);
+    hipError_t e;
+    for (int k = 0; k < 2; ++k) {
+        e = hipMalloc(&h->buf[k], pop_bytes);
+        if (e != hipSuccess) {
+            evlbm_destroy(h);
+            return fail(EVLBM_ENOMEM, "hipMalloc(%zu) for populations: %s", pop_bytes, hipGetErrorString(e));
+        }
+    }
+    e = hipMalloc(&h->m, m_bytes);
+    if (e == hipSuccess) e = hipMalloc(&h->lap, (size_t)h->N * real_bytes(storage));
+    if (e != hipSuccess) {
+        evlbm_destroy(h);
+        return fail(EVLBM_ENOMEM, "hipMalloc for moment fields: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return EVLBM_OK;
+}
+
+int evlbm_destroy(evlbm_t h)
+{
+    if (!h) return EVLBM_OK;
+    for (int k = 0; k < 2; ++k)
+        if (h->graph_exec_par[k]) hipGraphExecDestroy(h->graph_exec_par[k]);
+    for (int k = 0; k < 2; ++k)
+        if (h->buf[k]) hipFree(h->buf[k]);
+    if (h->m) hipFree(h->m);
+    if (h->lap) hipFree(h->lap);
+    if (h->scratch) hipFree(h->scratch);
+    delete h;
+    return EVLBM_OK;
+}
+
+static void invalidate_graph(evlbm_t h)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (h->graph_exec_par[k]) hipGraphExecDestroy(h->graph_exec_par[k]);
+        h->graph_exec_par[k] = nullptr;
+    }
+}
+
+int evlbm_set_eos(evlbm_t h, double R, double a, double b, double kappa)
+{
+    if (!h) return fail(EVLBM_EINVAL, "null handle");
+    if (!(R > 0) || !(a >= 0) || !(b >= 0) || !(kappa >= 0))
+        return fail(EVLBM_EINVAL, "need R > 0 and a, b, kappa >= 0");
+    h->R = R;
+    h->a = a;
+    h->b = b;
+    h->kappa = kappa;
+    invalidate_graph(h);
+    return EVLBM_OK;
+}
+
+int evlbm_set_relaxation(evlbm_t h, double tau, double lambda)
+{
+    if (!h) return fail(EVLBM_EINVAL, "null handle");
+    if (!(tau > 0) || !(lambda > 0)) return fail(EVLBM_EINVAL, "need tau > 0 and lambda > 0");
+    if (tau > lambda) return fail(EVLBM_EINVAL, "need lambda >= tau (effective relaxation time >= 0)");
+    h->tau = tau;
+    h->lambda = lambda;
+    invalidate_graph(h);
+    return EVLBM_OK;
+}
+
+int evlbm_set_option(evlbm_t h, int key, double value)
+{
+    if (!h) return fail(EVLBM_EINVAL, "null handle");
+    switch (key) {
+    case EVLBM_OPT_SPHI:
+        if (value != 1.0 && value != -1.0 && value != 0.0) return fail(EVLBM_EINVAL, "s_phi must be -1, 0 or +1");
+        h->sphi = value;
+        break;
+    case EVLBM_OPT_REF_RHO:
+        if (!(value > 0)) return fail(EVLBM_EINVAL, "reference density must be positive");
+        if (h->initialized) return fail(EVLBM_ESTATE, "set the deviation reference before initialisation");
+        h->ref_rho = value;
+        break;
+    case EVLBM_OPT_REF_T:
+        if (!(value > 0)) return fail(EVLBM_EINVAL, "reference temperature must be positive");
+        if (h->initialized) return fail(EVLBM_ESTATE, "set the deviation reference before initialisation");
+        h->ref_T = value;
+        break;
+    case EVLBM_OPT_CHECK_EVERY:
+        if (value < 0) return fail(EVLBM_EINVAL, "check interval must be >= 0");
+        h->check_every = (int64_t)value;
+        break;
+    case EVLBM_OPT_USE_GRAPH:
+        h->use_graph = value != 0.0;
+        break;
+    default:
+        return fail(EVLBM_EINVAL, "unknown option %d", key);
+    }
+    invalidate_graph(h);
+    return EVLBM_OK;
+}
+
+int evlbm_init_fields(evlbm_t h, const void *rho, const void *u, const void *T, int where)
+{
+    if (!h) return fail(EVLBM_EINVAL, "null handle");
+    if (!rho || !T) return fail(EVLBM_EINVAL, "rho and T are required");
+    if (where != EVLBM_HOST_F64 && where != EVLBM_DEVICE_F32 && where != EVLBM_DEVICE_F64)
+        return fail(EVLBM_EINVAL, "unknown location %d", where);
+    const long N = h->N;
+    const size_t need = sizeof(double) * N * (2 + h->D) + 64;
+    int rc = ensure_scratch(h, need);
+    if (rc) return rc;
+    double *d_rho = (double *)h->scratch;
+    double *d_T = d_rho + N;
+    double *d_u = u ? d_T + N : nullptr;
+    int *flag = (int *)(d_T + N + (long)h->D * N);
+    hipError_t e = hipSuccess;
+    if (where == EVLBM_HOST_F64) {
+        const double *hr = (const double *)rho, *ht = (const double *)T;
+        for (long c = 0; c < N; ++c) {
+            if (!std::isfinite(hr[c]) || !std::isfinite(ht[c]))
+                return fail(EVLBM_ENONFINITE, "non-finite initial field at cell %ld", c);
+            if (!(hr[c] > 0) || !(1.0 - h->b * hr[c] > 0) || !(ht[c] > 0))
+                return fail(EVLBM_ENONPHYS, "cell %ld: need rho > 0, b rho < 1, T > 0", c);
+        }
+        e = hipMemcpyAsync(d_rho, rho, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_T, T, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
+        if (e == hipSuccess && u)
+            e = hipMemcpyAsync(d_u, u, sizeof(double) * N * h->D, hipMemcpyHostToDevice, h->stream);
+    } else if (where == EVLBM_DEVICE_F64) {
+        e = hipMemcpyAsync(d_rho, rho, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(d_T, T, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess && u)
+            e = hipMemcpyAsync(d_u, u, sizeof(double) * N * h->D, hipMemcpyDeviceToDevice, h->stream);
+    } else {
+        const long nb = (N + 255) / 256;
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(nb), dim3(256), 0, h->stream, (const float *)rho, d_rho, N);
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(nb), dim3(256), 0, h->stream, (const float *)T, d_T, N);
+        if (u)
+            hipLaunchKernelGGL(k_f32_to_f64, dim3((N * h->D + 255) / 256), dim3(256), 0, h->stream, (const float *)u,
+                               d_u, N * h->D);
+    }
+    if (e != hipSuccess) return hip_fail(e, "copying initial fields");
+    if (where != EVLBM_HOST_F64) {
+        int zero = 0, host = 0;
+        e = hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        hipLaunchKernelGGL(k_validate, dim3((N + 255) / 256), dim3(256), 0, h->stream, d_rho, d_T, N, h->b, flag);
+        e = hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "validating initial fields");
+        if (host & 2) return fail(EVLBM_ENONFINITE, "non-finite initial field");
+        if (host & 1) return fail(EVLBM_ENONPHYS, "need rho > 0, b rho < 1, T > 0 everywhere");
+    }
+    h->cur = 0;
+    dispatch<RunInit>(h, (const double *)d_rho, (const double *)d_u, (const double *)d_T);
+    rc = check_launch("k_init");
+    if (rc) return rc;
+    h->step = 0;
+    h->initialized = true;
+    h->m_valid = false;
+    invalidate_graph(h);
+    // the scratch buffer is reused by later calls: finish before returning
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return EVLBM_OK;
+}
+
+int evlbm_step(evlbm_t h, int64_t nsteps)
+{
+    if (!h) return fail(EVLBM_EINVAL, "null handle");
+    if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
+    if (nsteps < 0) return fail(EVLBM_EINVAL, "nsteps must be >= 0");
+    int64_t done = 0;
+    while (done < nsteps) {
+        int64_t chunk = nsteps - done;
+        if (h->check_every > 0) {
+            const int64_t to_check = h->check_every - (h->step % h->check_every);
+            if (chunk > to_check) chunk = to_check;
+        }
+        int rc = run_steps(h, chunk);
+        if (rc) return rc;
+        done += chunk;
+        if (h->check_every > 0 && h->step % h->check_every == 0) {
+            rc = scan_nonfinite(h);
+            if (rc) return rc;
+        }
+    }
+    return check_launch("evlbm_step");
+}
+
+int evlbm_step_count(evlbm_t h, int64_t *out)
+{
+    if (!h || !out) return fail(EVLBM_EINVAL, "null argument");
+    *out = h->step;
+    return EVLBM_OK;
+}
+
+int evlbm_read_moments(evlbm_t h, void *rho, void *u, void *T, int where)
+{
+    if (!h) return fail(EVLBM_EINVAL, "null handle");
+    if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
+    if (where != EVLBM_HOST_F64 && where != EVLBM_DEVICE_F32 && where != EVLBM_DEVICE_F64)
+        return fail(EVLBM_EINVAL, "unknown location %d", where);
+    refresh_moments(h);
+    dispatch<RunLap>(h);
+    const long N = h->N;
+    if (where == EVLBM_DEVICE_F32) {
+        dispatch<RunReadoutF>(h, (float *)rho, (float *)u, (float *)T);
+        return check_launch("readout");
+    }
+    if (where == EVLBM_DEVICE_F64) {
+        dispatch<RunReadoutD>(h, (double *)rho, (double *)u, (double *)T);
+        return check_launch("readout");
+    }
+    int rc = ensure_scratch(h, sizeof(double) * N * (2 + h->D));
+    if (rc) return rc;
+    double *d_rho = (double *)h->scratch, *d_T = d_rho + N, *d_u = d_T + N;
+    dispatch<RunReadoutD>(h, d_rho, d_u, d_T);
+    rc = check_launch("readout");
+    if (rc) return rc;
+    hipError_t e = hipSuccess;
+    if (rho) e = hipMemcpyAsync(rho, d_rho, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && T) e = hipMemcpyAsync(T, d_T, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u, d_u, sizeof(double) * N * h->D, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying moments to the host");
+    return EVLBM_OK;
+}
+
+int evlbm_global_sums(evlbm_t h, double out[8])
+{
+    if (!h || !out) return fail(EVLBM_EINVAL, "null argument");
+    if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
+    refresh_moments(h);
+    dispatch<RunLap>(h);
+    const long nb = (h->N + 255) / 256;
+    int rc = ensure_scratch(h, sizeof(double) * (nb * 9 + 16));
+    if (rc) return rc;
+    dispatch<RunSums>(h, (double *)h->scratch, nb);
+    rc = check_launch("k_sums");
+    if (rc) return rc;
+    const int ops[8] = {0, 0, 0, 0, 0, 0, 1, 2};
+    return finish_reduce(h, nb, 8, ops, out);
+}
+
+int evlbm_measure(evlbm_t h, int kind, const double *geom, double out[8])
+{
+    if (!h || !geom || !out) return fail(EVLBM_EINVAL, "null argument");
+    if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
+    if (kind != EVLBM_MEASURE_SLAB && kind != EVLBM_MEASURE_DROPLET) return fail(EVLBM_EINVAL, "unknown kind %d", kind);
+    refresh_moments(h);
+    dispatch<RunLap>(h);
+    const long nb = (h->N + 255) / 256;
+    int rc = ensure_scratch(h, sizeof(double) * (nb * 9 + 16));
+    if (rc) return rc;
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < (kind == EVLBM_MEASURE_SLAB ? 6 : 5); ++k) g[k] = geom[k];
+    dispatch<RunMeasure>(h, kind, (const double *)g, (double *)h->scratch, nb);
+    rc = check_launch("k_measure");
+    if (rc) return rc;
+    // nine sums; the final reduction runs 8 lanes, so reduce the ninth on the host
+    const int ops[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double s[8];
+    rc = finish_reduce(h, nb, 9, ops, s);
+    if (rc) return rc;
+    std::vector<double> part((size_t)nb * 9);
+    hipError_t e = hipMemcpy(part.data(), h->scratch, sizeof(double) * nb * 9, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    double total = 0.0;
+    for (long b = 0; b < nb; ++b) total += part[b * 9 + 8];
+    const double n_in = s[3], n_out = s[7];
+    const double rin = n_in > 0 ? s[0] / n_in : NAN, rout = n_out > 0 ? s[4] / n_out : NAN;
+    out[0] = rin;
+    out[1] = rout;
+    out[2] = n_in > 0 ? s[1] / n_in : NAN;
+    out[3] = n_out > 0 ? s[5] / n_out : NAN;
+    out[4] = n_in > 0 ? s[2] / n_in : NAN;
+    out[5] = n_out > 0 ? s[6] / n_out : NAN;
+    double Re = NAN;
+    if (kind == EVLBM_MEASURE_DROPLET && n_in > 0 && n_out > 0) {
+        const double vol = (total - (double)h->N * rout) / (rin - rout);
+        Re = h->D == 2 || h->nz == 1 ? std::sqrt(vol / M_PI) : std::cbrt(3.0 * vol / (4.0 * M_PI));
+    }
+    out[6] = Re;
+    out[7] = n_in;
+    return EVLBM_OK;
+}
+
+int evlbm_get_populations(evlbm_t h, void *f, void *g, int where)
+{
+    if (!h || !f || !g) return fail(EVLBM_EINVAL, "null argument");
+    if (where != EVLBM_HOST_F64 && where != EVLBM_DEVICE_F64) return fail(EVLBM_EINVAL, "populations are FP64");
+    const size_t half = sizeof(double) * h->N * h->Q;
+    int rc = ensure_scratch(h, 2 * half);
+    if (rc) return rc;
+    dispatch<RunDecode>(h, (double *)h->scratch);
+    rc = check_launch("k_decode");
+    if (rc) return rc;
+    const hipMemcpyKind k = where == EVLBM_HOST_F64 ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    hipError_t e = hipMemcpyAsync(f, h->scratch, half, k, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(g, (char *)h->scratch + half, half, k, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying populations");
+    return EVLBM_OK;
+}
+
+int evlbm_set_populations(evlbm_t h, const void *f, const void *g, int where)
+{
+    if (!h || !f || !g) return fail(EVLBM_EINVAL, "null argument");
+    if (where != EVLBM_HOST_F64 && where != EVLBM_DEVICE_F64) return fail(EVLBM_EINVAL, "populations are FP64");
+    const size_t half = sizeof(double) * h->N * h->Q;
+    int rc = ensure_scratch(h, 2 * half);
+    if (rc) return rc;
+    const hipMemcpyKind k = where == EVLBM_HOST_F64 ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    hipError_t e = hipMemcpyAsync(h->scratch, f, half, k, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync((char *)h->scratch + half, g, half, k, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "copying populations");
+    dispatch<RunEncode>(h, (const double *)h->scratch);
+    rc = check_launch("k_encode");
+    if (rc) return rc;
+    h->initialized = true;
+    h->m_valid = false;
+    invalidate_graph(h);
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return EVLBM_OK;
+}
+
+int evlbm_checkpoint_save(evlbm_t h, const char *path)
+{
+    if (!h || !path) return fail(EVLBM_EINVAL, "null argument");
+    if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
+    const size_t bytes = (size_t)h->N * 2 * h->Q * store_bytes(h->storage);
+    std::vector<char> host(bytes);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(host.data(), h->buf[h->cur], bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "copying populations");
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return fail(EVLBM_EIO, "cannot open %s", path);
+    char hdr[512];
+    int n = snprintf(hdr, sizeof(hdr),
+                     "{\"format\":\"evlbm-1\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "\"R\":%.17g,\"a\":%.17g,\"b\":%.17g,\"kappa\":%.17g,\"tau\":%.17g,\"lambda\":%.17g,"
+                     "\"sphi\":%.17g,\"ref_rho\":%.17g,\"ref_T\":%.17g,\"step\":%lld,\"bytes\":%zu}\n",
+                     h->D, h->nx, h->ny, h->nz, h->storage, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi,
+                     h->ref_rho, h->ref_T, (long long)h->step, bytes);
+    bool ok = fwrite(hdr, 1, n, fp) == (size_t)n && fwrite(host.data(), 1, bytes, fp) == bytes;
+    ok = (fclose(fp) == 0) && ok;
+    if (!ok) return fail(EVLBM_EIO, "writing %s failed", path);
+    return EVLBM_OK;
+}
+
+int evlbm_checkpoint_load(evlbm_t h, const char *path)
+{
+    if (!h || !path) return fail(EVLBM_EINVAL, "null argument");
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return fail(EVLBM_EIO, "cannot open %s", path);
+    char hdr[1024];
+    if (!fgets(hdr, sizeof(hdr), fp)) {
+        fclose(fp);
+        return fail(EVLBM_EIO, "empty checkpoint %s", path);
+    }
+    int D = 0, nx = 0, ny = 0, nz = 0, st = -1;
+    long long step = 0;
+    double R, a, b, kappa, tau, lam, sphi, rr, rt;
+    size_t bytes = 0;
+    int got = sscanf(hdr,
+                     "{\"format\":\"evlbm-1\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "\"R\":%lg,\"a\":%lg,\"b\":%lg,\"kappa\":%lg,\"tau\":%lg,\"lambda\":%lg,"
+                     "\"sphi\":%lg,\"ref_rho\":%lg,\"ref_T\":%lg,\"step\":%lld,\"bytes\":%zu}",
+                     &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &rr, &rt, &step, &bytes);
+    if (got != 16) {
+        fclose(fp);
+        return fail(EVLBM_EIO, "bad checkpoint header in %s", path);
+    }
+    if (D != h->D || nx != h->nx || ny != h->ny || nz != h->nz || st != h->storage) {
+        fclose(fp);
+        return fail(EVLBM_EINVAL, "checkpoint lattice/sizes/storage differ from the handle");
+    }
+    std::vector<char> host(bytes);
+    const bool ok = fread(host.data(), 1, bytes, fp) == bytes;
+    fclose(fp);
+    if (!ok) return fail(EVLBM_EIO, "truncated checkpoint %s", path);
+    h->R = R;
+    h->a = a;
+    h->b = b;
+    h->kappa = kappa;
+    h->tau = tau;
+    h->lambda = lam;
+    h->sphi = sphi;
+    h->ref_rho = rr;
+    h->ref_T = rt;
+    h->cur = 0;
+    hipError_t e = hipMemcpy(h->buf[0], host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "copying populations");
+    h->step = step;
+    h->initialized = true;
+    h->m_valid = false;
+    invalidate_graph(h);
+    return EVLBM_OK;
+}
+
+int evlbm_profile_step(evlbm_t h, int nsteps, double out[2])
+{
+    if (!h || !out || nsteps <= 0 || nsteps > 4096) return fail(EVLBM_EINVAL, "need 0 < nsteps <= 4096");
+    if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
+    std::vector<hipEvent_t> ev((size_t)3 * nsteps, nullptr);
+    hipError_t e = hipSuccess;
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    if (e == hipSuccess) {
+        for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+            e = hipEventRecord(ev[3 * k], h->stream);
+            h->m_valid = false;
+            refresh_moments(h);
+            if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], h->stream);
+            launch_step(h);
+            if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], h->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    }
+    double tm = 0.0, tc = 0.0;
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+        float a = 0.f, b = 0.f;
+        e = hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+        tm += a;
+        tc += b;
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(e, "profiling the step kernels");
+    out[0] = tm / nsteps;
+    out[1] = tc / nsteps;
+    return EVLBM_OK;
+}
+
+int evlbm_synchronize(evlbm_t h)
+{
+    if (!h) return fail(EVLBM_EINVAL, "null handle");
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return EVLBM_OK;
+}
+
+int evlbm_eos_coexistence(double R, double a, double b, double T, double out[3])
+{
+    if (!out || !(R > 0) || !(a > 0) || !(b > 0)) return fail(EVLBM_EINVAL, "need R, a, b > 0");
+    const double Tc = 8.0 * a / (27.0 * b * R);
+    if (!(T > 0) || !(T < Tc)) return fail(EVLBM_EINVAL, "T must lie in (0, T_c)");
+    const double RT = R * T, rc = 1.0 / (3.0 * b), s = std::sqrt(1.0 - T / Tc);
+    auto P = [&](double r) { return r * RT / (1.0 - b * r) - a * r * r; };
+    auto dP = [&](double r) { return RT / ((1.0 - b * r) * (1.0 - b * r)) - 2.0 * a * r; };
+    auto mu = [&](double r) { return RT * std::log(r / (1.0 - b * r)) + RT / (1.0 - b * r) - 2.0 * a * r; };
+    // start from the mean-field critical law and keep the iterates on their branches
+    double rl = std::fmin(rc * (1.0 + 2.0 * s), 0.98 / b), rv = std::fmax(rc * (1.0 - 2.0 * s), 1e-3 * rc);
+    for (int it = 0; it < 200; ++it) {
+        const double f1 = P(rl) - P(rv), f2 = mu(rl) - mu(rv);
+        const double a11 = dP(rl), a12 = -dP(rv), a21 = dP(rl) / rl, a22 = -dP(rv) / rv;
+        const double det = a11 * a22 - a12 * a21;
+        double drl = -(f1 * a22 - a12 * f2) / det, drv = -(a11 * f2 - a21 * f1) / det;
+        double t = 1.0;
+        while ((rl + t * drl >= 1.0 / b || rl + t * drl <= rc || rv + t * drv <= 0.0 || rv + t * drv >= rc) && t > 1e-6)
+            t *= 0.5;
+        rl += t * drl;
+        rv += t * drv;
+        if (std::fabs(drl) < 1e-15 * rl && std::fabs(drv) < 1e-15 * rv) break;
+    }
+    out[0] = rl;
+    out[1] = rv;
+    out[2] = P(rl);
+    return EVLBM_OK;
+}
+
+}  // extern "C"
+

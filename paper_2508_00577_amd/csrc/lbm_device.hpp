@@ -1,0 +1,201 @@
+// Device-side building blocks of the Enskog-Vlasov lattice Boltzmann step
+// (Karlin & Hosseini, arXiv 2508.00577) for gfx950: lattice constants,
+// 16-bit deviation codecs, isotropic stencils on LDS tiles and the per-axis
+// factors of the product equilibria.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "evlbm.h"
+
+namespace evlbm {
+
+template <int D>
+struct Lat {
+    static constexpr int Q = (D == 2) ? 9 : 27;
+    static constexpr int HZ = (D == 3) ? 1 : 0;  // 1 where the z direction exists
+};
+
+// Velocity index i = (cx+1) + 3 (cy+1) + 9 (cz+1) on D3Q27; D2Q9 uses the
+// first nine indices i = (cx+1) + 3 (cy+1) with cz = 0.
+__host__ __device__ constexpr int cx_of(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int cy_of(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int cz_of(int i) { return (i / 9) % 3 - 1; }
+template <int D>
+__host__ __device__ constexpr int cz_d(int i) { return D == 3 ? cz_of(i) : 0; }
+
+// 1D lattice weights: 2/3 for c = 0, 1/6 for c = +-1 (their products are the
+// D2Q9 / D3Q27 weights).
+template <typename R>
+__host__ __device__ constexpr R w1(int c) { return c == 0 ? R(2) / R(3) : R(1) / R(6); }
+
+__host__ __device__ inline int wrapi(int v, int n)
+{
+    int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// ------------------------------------------------------------------ codecs
+
+__device__ inline uint16_t f32_to_bf16_rne(float v)
+{
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+__device__ inline uint16_t f32_to_f16_rne(float v)
+{
+    _Float16 h = (_Float16)v;  // v_cvt_f16_f32 rounds to nearest even
+    return __builtin_bit_cast(uint16_t, h);
+}
+
+__device__ inline float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+
+// Storage traits: T = stored type, R = arithmetic type.
+template <int S>
+struct Codec;
+
+template <>
+struct Codec<EVLBM_F64> {
+    using T = double;
+    using R = double;
+    static __device__ inline R dec(T v, R) { return v; }
+    static __device__ inline T enc(R v, R) { return v; }
+};
+
+template <>
+struct Codec<EVLBM_F32> {
+    using T = float;
+    using R = float;
+    static __device__ inline R dec(T v, R) { return v; }
+    static __device__ inline T enc(R v, R) { return v; }
+};
+
+template <>
+struct Codec<EVLBM_F16DEV> {
+    using T = uint16_t;
+    using R = float;
+    static __device__ inline R dec(T v, R ref) { return ref + f16_to_f32(v); }
+    static __device__ inline T enc(R v, R ref) { return f32_to_f16_rne(v - ref); }
+};
+
+template <>
+struct Codec<EVLBM_BF16DEV> {
+    using T = uint16_t;
+    using R = float;
+    static __device__ inline R dec(T v, R ref) { return ref + bf16_to_f32(v); }
+    static __device__ inline T enc(R v, R ref) { return f32_to_bf16_rne(v - ref); }
+};
+
+// ------------------------------------------------------------ parameters
+
+template <typename R>
+struct StepParams {
+    int nx, ny, nz;
+    long N;
+    R a, b, kappa;   // EOS: P_E = rho RT/(1 - b rho), P_V = -a rho^2, capillarity
+    R two_beta;      // 2 beta, beta = 1/(2 tau + 1)
+    R wstar;         // (dt/lambda)(1 - beta)
+    R lambda, sphi;
+    R Rgas;
+    R ref[54];       // reference populations of the deviation storage: f (Q) then g (Q)
+};
+
+// ---------------------------------------------- per-axis equilibrium factors
+
+// psi(c; xi, zeta) of eq. phi, indexed by k = c + 1:
+// psi(0) = 1 - zeta, psi(+-1) = (zeta +- xi)/2.
+template <typename R>
+__device__ inline void psi3(R xi, R zeta, R out[3])
+{
+    out[0] = R(0.5) * (zeta - xi);
+    out[1] = R(1) - zeta;
+    out[2] = R(0.5) * (zeta + xi);
+}
+
+// Operator factors of the energy equilibrium (eq. geq) on A = u^2/2 with
+// O A = theta dA/du + u A:  O A = theta u + u^3/2,
+// O^2 A = theta^2 + (5/2) theta u^2 + u^4/2;  chi(0) = A - O^2 A,
+// chi(+-1) = (O^2 A +- O A)/2.  With phi = psi(c; u, theta + u^2):
+// g_i = rho [ (3/2) RT prod_a phi_a + sum_b chi_b prod_{a != b} phi_a ].
+template <typename R>
+__device__ inline void chi3(R u, R theta, R out[3])
+{
+    R u2 = u * u;
+    R A = R(0.5) * u2;
+    R OA = theta * u + R(0.5) * u2 * u;
+    R O2A = theta * theta + R(2.5) * theta * u2 + R(0.5) * u2 * u2;
+    out[0] = R(0.5) * (O2A - OA);
+    out[1] = A - O2A;
+    out[2] = R(0.5) * (O2A + OA);
+}
+
+// ------------------------------------------------- isotropic LDS stencils
+
+// d_a phi = 3 sum_i w_i c_ia phi(x + c_i) on an LDS box with strides (1, sy, sz).
+template <int D, int A, typename R>
+__device__ inline R lds_grad(const R *s, int c, int sy, int sz)
+{
+    constexpr int HZ = Lat<D>::HZ;
+    R acc = R(0);
+#pragma unroll
+    for (int dz = -HZ; dz <= HZ; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int ca = (A == 0) ? dx : (A == 1) ? dy : dz;
+                if (ca == 0) continue;
+                const R w = w1<R>(dx) * w1<R>(dy) * (D == 3 ? w1<R>(dz) : R(1));
+                acc += (R(3) * w * R(ca)) * s[c + dx + dy * sy + dz * sz];
+            }
+    return acc;
+}
+
+// lap phi = 6 sum_i w_i (phi(x + c_i) - phi(x)).
+template <int D, typename R>
+__device__ inline R lds_lap(const R *s, int c, int sy, int sz)
+{
+    constexpr int HZ = Lat<D>::HZ;
+    R acc = R(0);
+    const R centre = s[c];
+#pragma unroll
+    for (int dz = -HZ; dz <= HZ; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0 && dz == 0) continue;
+                const R w = w1<R>(dx) * w1<R>(dy) * (D == 3 ? w1<R>(dz) : R(1));
+                acc += (R(6) * w) * (s[c + dx + dy * sy + dz * sz] - centre);
+            }
+    return acc;
+}
+
+// Gradient of rho^2 from an LDS box of rho (the conservative mean-field force).
+template <int D, int A, typename R>
+__device__ inline R lds_grad_sq(const R *s, int c, int sy, int sz)
+{
+    constexpr int HZ = Lat<D>::HZ;
+    R acc = R(0);
+#pragma unroll
+    for (int dz = -HZ; dz <= HZ; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int ca = (A == 0) ? dx : (A == 1) ? dy : dz;
+                if (ca == 0) continue;
+                const R w = w1<R>(dx) * w1<R>(dy) * (D == 3 ? w1<R>(dz) : R(1));
+                const R v = s[c + dx + dy * sy + dz * sz];
+                acc += (R(3) * w * R(ca)) * (v * v);
+            }
+    return acc;
+}
+
+}  // namespace evlbm

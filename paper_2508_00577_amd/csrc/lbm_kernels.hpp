@@ -1,0 +1,568 @@
+// HIP kernels of one lattice: initialisation, pulled moments, the fused
+// stencil + collision step, readout, FP64 reductions and region means.
+//
+// One time step (eq. pre_LBM) is two launches:
+//   k_moments  pull f, g (H1) and form rho, j = sum c f, e = sum g (H2) into a
+//              moment field;
+//   k_collide  stage rho (tile + 3 halo) in LDS, build lap rho, the force
+//              F = a grad(rho^2) + kappa rho grad(lap rho) (H3), the half-step
+//              fields u, RT, theta = RT/(1 - b rho) (H4) on tile + 1, the
+//              corrections Phi_aa, Phi', q' (H5) and shifted state (H6) on the
+//              tile, then per cell pull f, g again, evaluate the equilibria
+//              (H7), relax (H8) and store (H9).
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace evlbm {
+
+template <int S>
+using StoreT = typename Codec<S>::T;
+template <int S>
+using RealT = typename Codec<S>::R;
+
+// -------------------------------------------------------------- k_init
+
+// f = f^eq(rho, u, theta), g = g^eq(u, RT) with theta = RT/(1 - b rho)
+// (eq. feq, eq. geq); inputs in FP64, u may be null (rest).
+template <int D, int S>
+__global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, const double *__restrict__ u0,
+                                              const double *__restrict__ T0, StoreT<S> *__restrict__ pop,
+                                              StepParams<RealT<S>> p)
+{
+    using R = RealT<S>;
+    constexpr int Q = Lat<D>::Q;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= p.N) return;
+    const double rho = rho0[cell];
+    const double RT = (double)p.Rgas * T0[cell];
+    const double theta = RT / (1.0 - (double)p.b * rho);
+    double u[3] = {0.0, 0.0, 0.0};
+    if (u0)
+        for (int a = 0; a < D; ++a) u[a] = u0[a * p.N + cell];
+    double fe[3][3], xe[3][3];
+    for (int a = 0; a < 3; ++a) {
+        if (a < D) {
+            psi3<double>(u[a], theta + u[a] * u[a], fe[a]);
+            chi3<double>(u[a], theta, xe[a]);
+        } else {
+            fe[a][0] = fe[a][2] = 0.0;
+            fe[a][1] = 1.0;
+            xe[a][0] = xe[a][1] = xe[a][2] = 0.0;
+        }
+    }
+    const double h = 1.5 * RT;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
+        const double f = rho * fe[0][kx] * fe[1][ky] * fe[2][kz];
+        const double g = rho * ((h * fe[0][kx] + xe[0][kx]) * fe[1][ky] * fe[2][kz] +
+                                fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
+        pop[(long)i * p.N + cell] = Codec<S>::enc((R)f, p.ref[i]);
+        pop[(long)(Q + i) * p.N + cell] = Codec<S>::enc((R)g, p.ref[Q + i]);
+    }
+}
+
+// ------------------------------------------------------------ k_moments
+
+// m[0] = rho, m[1..D] = j, m[D+1] = e of the pulled populations
+// fh_i(x) = f_i(x - c_i).  Grid (ceil(nx/bx), ny, nz), block (bx).
+template <int D, int S>
+__global__ void __launch_bounds__(256) k_moments(const StoreT<S> *__restrict__ pop, RealT<S> *__restrict__ m,
+                                                 StepParams<RealT<S>> p)
+{
+    using R = RealT<S>;
+    constexpr int Q = Lat<D>::Q;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= p.nx) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    // source coordinate x - c for c = -1, 0, +1
+    const int xs[3] = {x + 1 == p.nx ? 0 : x + 1, x, x == 0 ? p.nx - 1 : x - 1};
+    const int ys[3] = {y + 1 == p.ny ? 0 : y + 1, y, y == 0 ? p.ny - 1 : y - 1};
+    const int zs[3] = {z + 1 == p.nz ? 0 : z + 1, z, z == 0 ? p.nz - 1 : z - 1};
+    R rho = R(0), jx = R(0), jy = R(0), jz = R(0), e = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
+        const long src = (long)xs[kx] + (long)p.nx * ((long)ys[ky] + (long)p.ny * zs[kz]);
+        const R f = Codec<S>::dec(pop[(long)i * p.N + src], p.ref[i]);
+        const R g = Codec<S>::dec(pop[(long)(Q + i) * p.N + src], p.ref[Q + i]);
+        rho += f;
+        e += g;
+        if (cx_of(i) == 1) jx += f;
+        if (cx_of(i) == -1) jx -= f;
+        if (cy_of(i) == 1) jy += f;
+        if (cy_of(i) == -1) jy -= f;
+        if (cz_d<D>(i) == 1) jz += f;
+        if (cz_d<D>(i) == -1) jz -= f;
+    }
+    const long cell = (long)x + (long)p.nx * ((long)y + (long)p.ny * z);
+    m[cell] = rho;
+    m[p.N + cell] = jx;
+    m[2 * p.N + cell] = jy;
+    if (D == 3) m[3 * p.N + cell] = jz;
+    m[(D + 1) * p.N + cell] = e;
+}
+
+// ------------------------------------------------------------ k_collide
+
+template <int D, int BX, int BY, int BZ>
+struct TileShape {
+    static constexpr int HZ = Lat<D>::HZ;
+    static constexpr int R3X = BX + 6, R3Y = BY + 6, R3Z = BZ + 6 * HZ;
+    static constexpr int R2X = BX + 4, R2Y = BY + 4, R2Z = BZ + 4 * HZ;
+    static constexpr int R1X = BX + 2, R1Y = BY + 2, R1Z = BZ + 2 * HZ;
+    static constexpr int N3 = R3X * R3Y * R3Z, N2 = R2X * R2Y * R2Z, N1 = R1X * R1Y * R1Z;
+    // fields kept on tile + 1: u (D), M = rho u (u^2 + 3 theta - 1) (D), F (D),
+    // theta - RT, K = (3/2) RT
+    static constexpr int NF = 3 * D + 2;
+    static constexpr int NT = BX * BY * BZ;
+};
+
+template <int D, int S, int BX, int BY, int BZ>
+__global__ void __launch_bounds__(BX *BY *BZ)
+    k_collide(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
+              StepParams<RealT<S>> p)
+{
+    using R = RealT<S>;
+    using TS = TileShape<D, BX, BY, BZ>;
+    constexpr int Q = Lat<D>::Q;
+    constexpr int HZ = TS::HZ;
+    constexpr int F_U = 0, F_M = D, F_F = 2 * D, F_TD = 3 * D, F_K = 3 * D + 1;
+    __shared__ R s_rho[TS::N3];
+    __shared__ R s_lap[TS::N2];
+    __shared__ R s_f1[TS::NF * TS::N1];
+
+    const int tid = threadIdx.x + BX * (threadIdx.y + BY * threadIdx.z);
+    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * BY, z0 = blockIdx.z * BZ;
+    const long N = p.N;
+
+    // rho on the tile + 3 halo (periodic)
+    for (int t = tid; t < TS::N3; t += TS::NT) {
+        const int lx = t % TS::R3X, ly = (t / TS::R3X) % TS::R3Y, lz = t / (TS::R3X * TS::R3Y);
+        const int gx = wrapi(x0 + lx - 3, p.nx), gy = wrapi(y0 + ly - 3, p.ny);
+        const int gz = HZ ? wrapi(z0 + lz - 3, p.nz) : 0;
+        s_rho[t] = m[(long)gx + (long)p.nx * ((long)gy + (long)p.ny * gz)];
+    }
+    __syncthreads();
+
+    // lap rho on tile + 2
+    for (int t = tid; t < TS::N2; t += TS::NT) {
+        const int lx = t % TS::R2X, ly = (t / TS::R2X) % TS::R2Y, lz = t / (TS::R2X * TS::R2Y);
+        const int c3 = (lx + 1) + TS::R3X * ((ly + 1) + TS::R3Y * (lz + HZ));
+        s_lap[t] = lds_lap<D, R>(s_rho, c3, TS::R3X, TS::R3X * TS::R3Y);
+    }
+    __syncthreads();
+
+    // force and half-step fields on tile + 1 (eq. EVforce1 under eq. P0E;
+    // eq. u_shift, eq. T_shift with Qtilde = 0)
+    for (int t = tid; t < TS::N1; t += TS::NT) {
+        const int lx = t % TS::R1X, ly = (t / TS::R1X) % TS::R1Y, lz = t / (TS::R1X * TS::R1Y);
+        const int c3 = (lx + 2) + TS::R3X * ((ly + 2) + TS::R3Y * (lz + 2 * HZ));
+        const int c2 = (lx + 1) + TS::R2X * ((ly + 1) + TS::R2Y * (lz + HZ));
+        const R rho = s_rho[c3];
+        R F[3];
+        F[0] = p.a * lds_grad_sq<D, 0, R>(s_rho, c3, TS::R3X, TS::R3X * TS::R3Y) +
+               p.kappa * rho * lds_grad<D, 0, R>(s_lap, c2, TS::R2X, TS::R2X * TS::R2Y);
+        F[1] = p.a * lds_grad_sq<D, 1, R>(s_rho, c3, TS::R3X, TS::R3X * TS::R3Y) +
+               p.kappa * rho * lds_grad<D, 1, R>(s_lap, c2, TS::R2X, TS::R2X * TS::R2Y);
+        F[2] = (D == 3) ? p.a * lds_grad_sq<D, 2, R>(s_rho, c3, TS::R3X, TS::R3X * TS::R3Y) +
+                              p.kappa * rho * lds_grad<D, 2, R>(s_lap, c2, TS::R2X, TS::R2X * TS::R2Y)
+                        : R(0);
+        const int gx = wrapi(x0 + lx - 1, p.nx), gy = wrapi(y0 + ly - 1, p.ny);
+        const int gz = HZ ? wrapi(z0 + lz - 1, p.nz) : 0;
+        const long cell = (long)gx + (long)p.nx * ((long)gy + (long)p.ny * gz);
+        R u[3], uF = R(0), u2 = R(0);
+        for (int a = 0; a < D; ++a) {
+            u[a] = (m[(a + 1) * N + cell] + R(0.5) * F[a]) / rho;
+            uF += u[a] * F[a];
+            u2 += u[a] * u[a];
+        }
+        const R rhoE = m[(D + 1) * N + cell] + R(0.5) * uF;
+        // K = (3/2) RT is kept as such: the energy equilibria need (3/2) RT and
+        // a round trip through a rounded 2/3 would bias the energy every step.
+        const R K = rhoE / rho - R(0.5) * u2;
+        const R RT = K * (R(2) / R(3));
+        const R theta = RT / (R(1) - p.b * rho);
+        for (int a = 0; a < D; ++a) {
+            s_f1[(F_U + a) * TS::N1 + t] = u[a];
+            s_f1[(F_M + a) * TS::N1 + t] = rho * u[a] * (u[a] * u[a] + R(3) * theta - R(1));
+            s_f1[(F_F + a) * TS::N1 + t] = F[a];
+        }
+        s_f1[F_TD * TS::N1 + t] = theta - RT;
+        s_f1[F_K * TS::N1 + t] = K;
+    }
+    __syncthreads();
+
+    const int lx = threadIdx.x, ly = threadIdx.y, lz = threadIdx.z;
+    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    if (x >= p.nx || y >= p.ny || z >= p.nz) return;
+    const int c1 = (lx + 1) + TS::R1X * ((ly + 1) + TS::R1Y * (lz + HZ));
+    const int c3 = (lx + 3) + TS::R3X * ((ly + 3) + TS::R3Y * (lz + 3 * HZ));
+    constexpr int SY = TS::R1X, SZ = TS::R1X * TS::R1Y;
+
+    const R rho = s_rho[c3];
+    const R inv_rho = R(1) / rho;
+    const R K = s_f1[F_K * TS::N1 + c1];  // (3/2) RT
+    const R RT = K * (R(2) / R(3));
+    const R one_m_br = R(1) - p.b * rho;
+    const R theta = RT / one_m_br;
+    const R P0 = rho * theta;
+    R u[3] = {R(0), R(0), R(0)}, F[3] = {R(0), R(0), R(0)};
+    for (int a = 0; a < D; ++a) {
+        u[a] = s_f1[(F_U + a) * TS::N1 + c1];
+        F[a] = s_f1[(F_F + a) * TS::N1 + c1];
+    }
+    // corrections (eq. correction_u, correction_gamma with gamma_0 of eq. gamma
+    // for P0 = P_E: gamma_0 = (5/3)/(1 - b rho); eq. correction_q)
+    R divu = lds_grad<D, 0, R>(s_f1 + F_U * TS::N1, c1, SY, SZ) +
+             lds_grad<D, 1, R>(s_f1 + (F_U + 1) * TS::N1, c1, SY, SZ);
+    if (D == 3) divu += lds_grad<D, 2, R>(s_f1 + (F_U + 2) * TS::N1, c1, SY, SZ);
+    const R Phip = P0 * (R(5) / R(3)) * (R(1) - R(1) / one_m_br) * divu;
+    R Phi[3] = {R(0), R(0), R(0)}, qp[3] = {R(0), R(0), R(0)};
+    Phi[0] = p.sphi * lds_grad<D, 0, R>(s_f1 + F_M * TS::N1, c1, SY, SZ) + Phip;
+    Phi[1] = p.sphi * lds_grad<D, 1, R>(s_f1 + (F_M + 1) * TS::N1, c1, SY, SZ) + Phip;
+    qp[0] = p.lambda * (P0 * lds_grad<D, 0, R>(s_f1 + F_TD * TS::N1, c1, SY, SZ) + u[0] * Phip);
+    qp[1] = p.lambda * (P0 * lds_grad<D, 1, R>(s_f1 + F_TD * TS::N1, c1, SY, SZ) + u[1] * Phip);
+    if (D == 3) {
+        Phi[2] = p.sphi * lds_grad<D, 2, R>(s_f1 + (F_M + 2) * TS::N1, c1, SY, SZ) + Phip;
+        qp[2] = p.lambda * (P0 * lds_grad<D, 2, R>(s_f1 + F_TD * TS::N1, c1, SY, SZ) + u[2] * Phip);
+    }
+    // shifted state (eq. def_ustar, Qtilde = 0)
+    R us[3], F2 = R(0);
+    for (int a = 0; a < 3; ++a) {
+        us[a] = u[a] + p.lambda * F[a] * inv_rho;
+        F2 += F[a] * F[a];
+    }
+    // (3/2) RT* = (3/2) RT - lambda^2 |F|^2/(2 rho^2)
+    const R hS = K - R(0.5) * p.lambda * p.lambda * F2 * inv_rho * inv_rho;
+    const R RTs = hS * (R(2) / R(3));
+    const R thetas = RTs / one_m_br;
+
+    // per-axis factors: fe (f^eq and g^eq), fs (f*), gs (g*), chi for g^eq, g*
+    R fe[3][3], fs[3][3], gs[3][3], xe[3][3], xs[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a < D) {
+            psi3<R>(u[a], theta + u[a] * u[a], fe[a]);
+            psi3<R>(us[a], theta + us[a] * us[a] + p.lambda * Phi[a] * inv_rho, fs[a]);
+            psi3<R>(us[a], thetas + us[a] * us[a], gs[a]);
+            chi3<R>(u[a], theta, xe[a]);
+            chi3<R>(us[a], thetas, xs[a]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                fe[a][k] = fs[a][k] = gs[a][k] = (k == 1) ? R(1) : R(0);
+                xe[a][k] = xs[a][k] = R(0);
+            }
+        }
+    }
+    const R hE = K;
+    const R omb = R(1) - p.two_beta;
+    const R c_eq = p.two_beta - p.wstar;
+
+    const int xs_[3] = {x + 1 == p.nx ? 0 : x + 1, x, x == 0 ? p.nx - 1 : x - 1};
+    const int ys_[3] = {y + 1 == p.ny ? 0 : y + 1, y, y == 0 ? p.ny - 1 : y - 1};
+    const int zs_[3] = {z + 1 == p.nz ? 0 : z + 1, z, z == 0 ? p.nz - 1 : z - 1};
+    const long cell = (long)x + (long)p.nx * ((long)y + (long)p.ny * z);
+
+    // The collision conserves mass and energy exactly: sum f_new = sum fh and
+    // sum g_new = sum gh + u.F (eq. pre_LBM with eq. u_shift, T_shift and
+    // Qtilde = 0).  The rest direction is stored last, as the exact (FP64)
+    // incoming sum minus the exact sum of the values actually stored in the
+    // other directions, so each cell keeps these balances to a single rounding
+    // of one stored value and no rounding bias accumulates from step to step.
+    constexpr int REST = (Q - 1) / 2;
+    const R fh_rest = Codec<S>::dec(src[(long)REST * N + cell], p.ref[REST]);
+    const R gh_rest = Codec<S>::dec(src[(long)(Q + REST) * N + cell], p.ref[Q + REST]);
+    double mass = (double)fh_rest, energy = (double)gh_rest, sf = 0.0, sg = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (i == REST) continue;
+        const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
+        const long s = (long)xs_[kx] + (long)p.nx * ((long)ys_[ky] + (long)p.ny * zs_[kz]);
+        const R fh = Codec<S>::dec(src[(long)i * N + s], p.ref[i]);
+        const R gh = Codec<S>::dec(src[(long)(Q + i) * N + s], p.ref[Q + i]);
+        const R Pyz_e = fe[1][ky] * fe[2][kz];
+        const R feq = rho * fe[0][kx] * Pyz_e;
+        const R fst = rho * fs[0][kx] * (fs[1][ky] * fs[2][kz]);
+        const R geq = rho * ((hE * fe[0][kx] + xe[0][kx]) * Pyz_e +
+                             fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
+        R gst = rho * ((hS * gs[0][kx] + xs[0][kx]) * (gs[1][ky] * gs[2][kz]) +
+                       gs[0][kx] * (xs[1][ky] * gs[2][kz] + gs[1][ky] * xs[2][kz]));
+        if (cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_d<D>(i) * cz_d<D>(i) == 1)
+            gst += R(0.5) * (R(cx_of(i)) * qp[0] + R(cy_of(i)) * qp[1] + R(cz_d<D>(i)) * qp[2]);
+        // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq)
+        const R fn = omb * fh + c_eq * feq + p.wstar * fst;
+        const R gn = omb * gh + c_eq * geq + p.wstar * gst;
+        const StoreT<S> fq = Codec<S>::enc(fn, p.ref[i]);
+        const StoreT<S> gq = Codec<S>::enc(gn, p.ref[Q + i]);
+        dst[(long)i * N + cell] = fq;
+        dst[(long)(Q + i) * N + cell] = gq;
+        mass += (double)fh;
+        energy += (double)gh;
+        sf += (double)Codec<S>::dec(fq, p.ref[i]);
+        sg += (double)Codec<S>::dec(gq, p.ref[Q + i]);
+    }
+    const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
+    dst[(long)REST * N + cell] = Codec<S>::enc((R)(mass - sf), p.ref[REST]);
+    dst[(long)(Q + REST) * N + cell] = Codec<S>::enc((R)(energy + uF - sg), p.ref[Q + REST]);
+}
+
+// ------------------------------------------------------------ readout
+
+// lap rho from the moment field (for the readout force).
+template <int D, typename R>
+__global__ void __launch_bounds__(256) k_lap_field(const R *__restrict__ m, R *__restrict__ lap, int nx, int ny, int nz)
+{
+    constexpr int HZ = Lat<D>::HZ;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    const R c = m[(long)x + (long)nx * ((long)y + (long)ny * z)];
+    R acc = R(0);
+    for (int dz = -HZ; dz <= HZ; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0 && dz == 0) continue;
+                const R w = w1<R>(dx) * w1<R>(dy) * (D == 3 ? w1<R>(dz) : R(1));
+                const long n = (long)wrapi(x + dx, nx) + (long)nx * ((long)wrapi(y + dy, ny) + (long)ny * wrapi(z + dz, nz));
+                acc += (R(6) * w) * (m[n] - c);
+            }
+    lap[(long)x + (long)nx * ((long)y + (long)ny * z)] = acc;
+}
+
+// Per-cell readout state: rho, u, RT, F, grad rho (all from the moment field
+// and its Laplacian, radius 1).
+template <int D, typename R>
+struct CellState {
+    R rho, u[3], RT, F[3], grad[3], rhoE;
+};
+
+template <int D, typename R>
+__device__ inline CellState<D, R> cell_state(const R *__restrict__ m, const R *__restrict__ lap, long N, int x, int y,
+                                             int z, int nx, int ny, int nz, R a, R kappa)
+{
+    constexpr int HZ = Lat<D>::HZ;
+    CellState<D, R> s;
+    const long cell = (long)x + (long)nx * ((long)y + (long)ny * z);
+    s.rho = m[cell];
+    R g2[3] = {R(0), R(0), R(0)}, gl[3] = {R(0), R(0), R(0)}, gr[3] = {R(0), R(0), R(0)};
+    for (int dz = -HZ; dz <= HZ; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const R w = R(3) * w1<R>(dx) * w1<R>(dy) * (D == 3 ? w1<R>(dz) : R(1));
+                const long n = (long)wrapi(x + dx, nx) + (long)nx * ((long)wrapi(y + dy, ny) + (long)ny * wrapi(z + dz, nz));
+                const R r = m[n], l = lap[n];
+                const int cc[3] = {dx, dy, dz};
+                for (int ax = 0; ax < D; ++ax) {
+                    g2[ax] += w * R(cc[ax]) * (r * r);
+                    gl[ax] += w * R(cc[ax]) * l;
+                    gr[ax] += w * R(cc[ax]) * r;
+                }
+            }
+    R uF = R(0), u2 = R(0);
+    for (int ax = 0; ax < 3; ++ax) {
+        s.F[ax] = (ax < D) ? a * g2[ax] + kappa * s.rho * gl[ax] : R(0);
+        s.grad[ax] = gr[ax];
+        s.u[ax] = (ax < D) ? (m[(ax + 1) * N + cell] + R(0.5) * s.F[ax]) / s.rho : R(0);
+        uF += s.u[ax] * s.F[ax];
+        u2 += s.u[ax] * s.u[ax];
+    }
+    s.rhoE = m[(D + 1) * N + cell] + R(0.5) * uF;
+    s.RT = (R(2) / R(3)) * (s.rhoE / s.rho - R(0.5) * u2);
+    return s;
+}
+
+template <int D, typename R, typename O>
+__global__ void __launch_bounds__(256) k_readout(const R *__restrict__ m, const R *__restrict__ lap, O *__restrict__ rho_out,
+                                                 O *__restrict__ u_out, O *__restrict__ T_out, int nx, int ny, int nz,
+                                                 R a, R kappa, R Rgas)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= nx) return;
+    const int y = blockIdx.y, z = blockIdx.z;
+    const long N = (long)nx * ny * nz;
+    const long cell = (long)x + (long)nx * ((long)y + (long)ny * z);
+    CellState<D, R> s = cell_state<D, R>(m, lap, N, x, y, z, nx, ny, nz, a, kappa);
+    if (rho_out) rho_out[cell] = (O)s.rho;
+    if (T_out) T_out[cell] = (O)(s.RT / Rgas);
+    if (u_out)
+        for (int aa = 0; aa < D; ++aa) u_out[aa * N + cell] = (O)s.u[aa];
+}
+
+// ------------------------------------------------------- FP64 reductions
+
+// Block-level FP64 sum of NV values, deterministic (fixed tree), then one
+// partial per block.  Op: 0 = sum, 1 = max, 2 = min.
+template <int NV>
+__device__ inline void block_reduce_store(double v[NV], const int ops[NV], double *__restrict__ partial)
+{
+    __shared__ double s_red[NV][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_xor(x, off, 64);
+            x = ops[k] == 0 ? x + o : ops[k] == 1 ? fmax(x, o) : fmin(x, o);
+        }
+        if (lane == 0) s_red[k][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int k = threadIdx.x;
+        double x = s_red[k][0];
+        for (int w = 1; w < nw; ++w) x = ops[k] == 0 ? x + s_red[k][w] : ops[k] == 1 ? fmax(x, s_red[k][w]) : fmin(x, s_red[k][w]);
+        partial[(long)blockIdx.x * NV + k] = x;
+    }
+}
+
+template <int NV>
+__global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__ partial, long nblocks, const int4 ops_lo,
+                                                      const int4 ops_hi, double *__restrict__ out)
+{
+    // one block of 64 threads per value: lane-strided partial sums then a
+    // fixed-order wave reduction (deterministic).
+    const int k = blockIdx.x;
+    const int ops[8] = {ops_lo.x, ops_lo.y, ops_lo.z, ops_lo.w, ops_hi.x, ops_hi.y, ops_hi.z, ops_hi.w};
+    const int op = ops[k];
+    double x = op == 0 ? 0.0 : op == 1 ? -1e300 : 1e300;
+    for (long b = threadIdx.x; b < nblocks; b += 64) {
+        const double v = partial[b * NV + k];
+        x = op == 0 ? x + v : op == 1 ? fmax(x, v) : fmin(x, v);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        double o = __shfl_xor(x, off, 64);
+        x = op == 0 ? x + o : op == 1 ? fmax(x, o) : fmin(x, o);
+    }
+    if (threadIdx.x == 0) out[k] = x;
+}
+
+// Global sums of the readout state (FP64 accumulation), one cell per thread
+// over a flat index.
+template <int D, int S>
+__global__ void __launch_bounds__(256) k_sums(const StoreT<S> *__restrict__ pop, const RealT<S> *__restrict__ m,
+                                              const RealT<S> *__restrict__ lap, StepParams<RealT<S>> p,
+                                              double *__restrict__ partial)
+{
+    using R = RealT<S>;
+    constexpr int Q = Lat<D>::Q;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 1e300};
+    const int ops[8] = {0, 0, 0, 0, 0, 0, 1, 2};
+    if (cell < p.N) {
+        const int x = (int)(cell % p.nx), y = (int)((cell / p.nx) % p.ny), z = (int)(cell / ((long)p.nx * p.ny));
+        CellState<D, R> s = cell_state<D, R>(m, lap, p.N, x, y, z, p.nx, p.ny, p.nz, p.a, p.kappa);
+        const double rho = s.rho;
+        double u2 = 0.0, g2 = 0.0;
+        v[0] = rho;
+        for (int a = 0; a < D; ++a) {
+            v[1 + a] = rho * (double)s.u[a];
+            u2 += (double)s.u[a] * (double)s.u[a];
+            g2 += (double)s.grad[a] * (double)s.grad[a];
+        }
+        v[4] = s.rhoE;
+        v[5] = (double)s.rhoE - (double)p.a * rho * rho + 0.5 * (double)p.kappa * g2;
+        v[6] = sqrt(u2);
+        const int xs[3] = {x + 1 == p.nx ? 0 : x + 1, x, x == 0 ? p.nx - 1 : x - 1};
+        const int ys[3] = {y + 1 == p.ny ? 0 : y + 1, y, y == 0 ? p.ny - 1 : y - 1};
+        const int zs[3] = {z + 1 == p.nz ? 0 : z + 1, z, z == 0 ? p.nz - 1 : z - 1};
+        double fmin_ = 1e300;
+        for (int i = 0; i < Q; ++i) {
+            const long src = (long)xs[cx_of(i) + 1] + (long)p.nx * ((long)ys[cy_of(i) + 1] + (long)p.ny * zs[cz_d<D>(i) + 1]);
+            const double f = Codec<S>::dec(pop[(long)i * p.N + src], p.ref[i]);
+            fmin_ = fmin(fmin_, f);
+        }
+        v[7] = fmin_;
+    }
+    block_reduce_store<8>(v, ops, partial);
+}
+
+// Region means for coexistence / Laplace measurements.
+// v = {sum rho_in, sum T_in, sum P_in, n_in, sum rho_out, sum T_out, sum P_out, n_out}
+// plus a separate sum of rho over the whole lattice (sums[8]).
+template <int D, typename R>
+__global__ void __launch_bounds__(256) k_measure(const R *__restrict__ m, const R *__restrict__ lap, int nx, int ny, int nz,
+                                                 R a, R b, R kappa, R Rgas, int kind, double g0, double g1, double g2,
+                                                 double g3, double g4, double g5, double *__restrict__ partial)
+{
+    const long N = (long)nx * ny * nz;
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int ops[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (cell < N) {
+        const int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((long)nx * ny));
+        CellState<D, R> s = cell_state<D, R>(m, lap, N, x, y, z, nx, ny, nz, a, kappa);
+        const double rho = s.rho, RT = s.RT;
+        const double P = rho * RT / (1.0 - (double)b * rho) - (double)a * rho * rho;
+        int region = 0;  // 1 in, 2 out
+        if (kind == EVLBM_MEASURE_SLAB) {
+            if (x >= g0 && x < g1) region = 1;
+            else if ((x >= g2 && x < g3) || (x >= g4 && x < g5)) region = 2;
+        } else {
+            const double dx = x - g0, dy = y - g1, dz = (D == 3) ? z - g2 : 0.0;
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r < g3) region = 1;
+            else if (r > g4) region = 2;
+        }
+        if (region == 1) {
+            v[0] = rho; v[1] = RT / (double)Rgas; v[2] = P; v[3] = 1.0;
+        } else if (region == 2) {
+            v[4] = rho; v[5] = RT / (double)Rgas; v[6] = P; v[7] = 1.0;
+        }
+        v[8] = rho;
+    }
+    block_reduce_store<9>(v, ops, partial);
+}
+
+// Count cells whose density is not finite and positive.
+template <typename R>
+__global__ void __launch_bounds__(256) k_scan_nonfinite(const R *__restrict__ m, long N, int *__restrict__ flag)
+{
+    const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= N) return;
+    const R r = m[cell];
+    if (!(r > R(0)) || !isfinite((double)r)) atomicAdd(flag, 1);
+}
+
+// Decode populations to FP64 / encode from FP64 (host I/O, checkpoints).
+template <int S>
+__global__ void __launch_bounds__(256) k_decode(const StoreT<S> *__restrict__ pop, double *__restrict__ out, long N, int Q2,
+                                                StepParams<RealT<S>> p)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * Q2) return;
+    const int i = (int)(t / N);
+    out[t] = (double)Codec<S>::dec(pop[t], p.ref[i]);
+}
+
+template <int S>
+__global__ void __launch_bounds__(256) k_encode(const double *__restrict__ in, StoreT<S> *__restrict__ pop, long N, int Q2,
+                                                StepParams<RealT<S>> p)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N * Q2) return;
+    const int i = (int)(t / N);
+    pop[t] = Codec<S>::enc((RealT<S>)in[t], p.ref[i]);
+}
+
+// Validate initial fields: rho > 0, b rho < 1, T > 0 and finite.
+__global__ void __launch_bounds__(256) k_validate(const double *__restrict__ rho, const double *__restrict__ T, long N,
+                                                  double b, int *__restrict__ flag)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const double r = rho[t], tt = T[t];
+    if (!isfinite(r) || !isfinite(tt)) atomicOr(flag, 2);
+    else if (!(r > 0.0) || !(1.0 - b * r > 0.0) || !(tt > 0.0)) atomicOr(flag, 1);
+}
+
+__global__ void __launch_bounds__(256) k_f32_to_f64(const float *__restrict__ in, double *__restrict__ out, long n)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (double)in[t];
+}
+
+}  // namespace evlbm

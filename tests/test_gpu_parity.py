@@ -1,0 +1,199 @@
+"""Parity of the HIP library with the FP64 oracle, through the C ABI.
+
+Norms: e_rho = max|d rho|/max|rho|, e_T = max|dT|/max|T| and
+e_u = max|du|/varsigma with varsigma = 1/sqrt(3) (the velocity is near zero
+at equilibrium, where j ~ -F/2 cancels, so it is measured against the lattice
+speed of sound).  Tolerances: 1e-10 for FP64 storage, 1e-5 for FP32.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.thermo as TH
+import synth
+
+pytestmark = pytest.mark.gpu
+
+ev = pytest.importorskip("paper_2508_00577_amd")
+P = synth.params()
+SQ3 = np.sqrt(3.0)
+
+
+def _errs(a, b):
+    (r1, u1, T1), (r2, u2, T2) = a, b
+    return (np.abs(r1 - r2).max() / np.abs(r2).max(), np.abs(u1 - u2).max() * SQ3,
+            np.abs(T1 - T2).max() / np.abs(T2).max())
+
+
+def _state(kind, shape, Tr, noise, seed=synth.SEED + 1):
+    T0 = Tr * synth.T_CRIT
+    rl, rv, _ = TH.coexistence(T0)
+    if kind == "slab":
+        rho = synth.slab(shape, rl, rv, noise=noise, seed=seed)
+    else:
+        R = 0.3 * min(s for s in shape if s > 1)
+        rho = synth.droplet(shape, R, rl, rv, noise=noise, seed=seed)
+    return rho, np.full(shape, T0)
+
+
+def _pair(D, shape, storage, rho, T, **kw):
+    nz, ny, nx = shape
+    q = dict(P)
+    q.update(kw)
+    g = ev.Lattice(D, nx, ny, nz, storage=storage)
+    g.set_params(**q)
+    g.init_fields(rho, T)
+    o = oracle.Lattice(D, nx, ny, nz)
+    o.set_params(**q)
+    o.init(rho, T)
+    return g, o
+
+
+def _compare(g, o, tol, label):
+    rg, ug, Tg = g.moments()
+    ro, uo, To, _ = o.moments()
+    e = _errs((rg, ug, Tg), (ro, uo, To))
+    print(f"{label}: e_rho={e[0]:.3e} e_u={e[1]:.3e} e_T={e[2]:.3e}", flush=True)
+    assert max(e) < tol, (label, e)
+    return e
+
+
+@pytest.mark.parametrize("D,shape", [(2, (1, 21, 70)), (3, (13, 11, 37))])
+def test_init_populations_match_oracle(D, shape):
+    rho, T = _state("droplet", shape, 0.8, 1e-4)
+    g, o = _pair(D, shape, "f64", rho, T)
+    fg, gg = g.get_populations()
+    fo, go = o.get_pops()
+    assert np.abs(fg - fo).max() < 1e-14 * np.abs(fo).max()
+    assert np.abs(gg - go).max() < 1e-14 * np.abs(go).max()
+
+
+@pytest.mark.parametrize("D,shape", [(2, (1, 21, 70)), (3, (9, 11, 37))])
+def test_one_step_populations_f64(D, shape):
+    """Every population after one step from the same (non-equilibrium) state."""
+    rho, T = _state("droplet", shape, 0.8, 1e-3)
+    g, o = _pair(D, shape, "f64", rho, T)
+    o.step(5)
+    f0, g0 = o.get_pops()
+    g.set_populations(f0, g0)
+    g.step(1)
+    o.step(1)
+    fg, gg = g.get_populations()
+    fo, go = o.get_pops()
+    ef = np.abs(fg - fo).max() / np.abs(fo).max()
+    eg = np.abs(gg - go).max() / np.abs(go).max()
+    print(f"one step D={D}: e_f={ef:.2e} e_g={eg:.2e}", flush=True)
+    assert ef < 1e-13 and eg < 1e-13
+
+
+def test_c1_flat_interface_f64_1000_steps():
+    """128 x 32 flat interface, T/Tc = 0.9, FP64: moments after 1, 100 and 1000 steps."""
+    shape = (1, 32, 128)
+    rho, T = _state("slab", shape, 0.9, 1e-3)
+    g, o = _pair(2, shape, "f64", rho, T)
+    _compare(g, o, 1e-12, "c1 f64 step 0")
+    for n, tol in ((1, 1e-12), (99, 1e-11), (900, 1e-10)):
+        g.step(n)
+        o.step(n)
+        _compare(g, o, tol, f"c1 f64 step {g.step_count}")
+
+
+def test_c1_flat_interface_f32_1000_steps():
+    shape = (1, 32, 128)
+    rho, T = _state("slab", shape, 0.9, 1e-3)
+    g, o = _pair(2, shape, "f32", rho, T)
+    g.step(1000)
+    o.step(1000)
+    _compare(g, o, 1e-5, "c1 f32 step 1000")
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_3d_droplet_ragged(storage, tol):
+    """D3Q27 droplet on a 37 x 11 x 13 lattice (several tiles, ragged tails)."""
+    shape = (13, 11, 37)
+    rho, T = _state("droplet", shape, 0.8, 1e-4)
+    g, o = _pair(3, shape, storage, rho, T)
+    g.step(60)
+    o.step(60)
+    _compare(g, o, tol, f"3d {storage} step 60")
+
+
+def test_2d_droplet_ragged_f32():
+    shape = (1, 53, 90)
+    rho, T = _state("droplet", shape, 0.7, 1e-4)
+    g, o = _pair(2, shape, "f32", rho, T)
+    g.step(400)
+    o.step(400)
+    _compare(g, o, 1e-5, "2d droplet f32 step 400")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_global_sums_match_oracle(storage):
+    shape = (1, 20, 48)
+    rho, T = _state("slab", shape, 0.85, 1e-3)
+    g, o = _pair(2, shape, storage, rho, T)
+    g.step(30)
+    o.step(30)
+    sg, so = g.global_sums(), o.global_sums()
+    tol = 1e-12 if storage == "f64" else 2e-6
+    assert sg[0] == pytest.approx(so[0], rel=tol)
+    assert sg[4] == pytest.approx(so[4], rel=tol)
+    assert sg[5] == pytest.approx(so[5], rel=tol)
+    assert sg[6] == pytest.approx(so[6], rel=1e-4 if storage == "f32" else 1e-9)
+    assert sg[7] == pytest.approx(so[7], rel=1e-5 if storage == "f32" else 1e-12)
+    assert np.abs(sg[1:4] - so[1:4]).max() < (1e-12 if storage == "f64" else 1e-5) * sg[0]
+
+
+def test_ideal_gas_limit_and_sphi_option():
+    """a = b = kappa = 0 with both signs of the Phi term, against the oracle."""
+    shape = (1, 1, 64)
+    x = np.arange(64)
+    rho = (1 + 1e-3 * np.cos(2 * np.pi * x / 64)).reshape(shape)
+    T = np.full(shape, 0.1)
+    for s in (-1.0, 1.0):
+        g, o = _pair(2, shape, "f64", rho, T, a=0.0, b=0.0, kappa=0.0, sphi=s)
+        g.step(200)
+        o.step(200)
+        _compare(g, o, 1e-11, f"ideal sphi={s}")
+
+
+def test_errors_are_reported():
+    with pytest.raises(ev.EvlbmError) as e:
+        ev.Lattice(2, 16, 16, 2)
+    assert e.value.name == "EINVAL"
+    g = ev.Lattice(2, 16, 16, 1, storage="f32")
+    with pytest.raises(ev.EvlbmError) as e:
+        g.set_relaxation(tau=2.0, lam=1.0)
+    assert e.value.name == "EINVAL"
+    with pytest.raises(ev.EvlbmError) as e:
+        g.step(1)
+    assert e.value.name == "ESTATE"
+    g.set_params(**P)
+    bad = np.full((1, 16, 16), 3.5)  # b rho > 1
+    with pytest.raises(ev.EvlbmError) as e:
+        g.init_fields(bad, np.full((1, 16, 16), 0.02))
+    assert e.value.name == "ENONPHYS"
+    nan = np.full((1, 16, 16), 0.5)
+    nan[0, 3, 3] = np.nan
+    with pytest.raises(ev.EvlbmError) as e:
+        g.init_fields(nan, np.full((1, 16, 16), 0.02))
+    assert e.value.name == "ENONFINITE"
+
+
+def test_graph_replay_matches_eager():
+    """Chunks replayed from captured graphs give the same bits as eager launches."""
+    shape = (1, 40, 96)
+    rho, T = _state("slab", shape, 0.8, 1e-3)
+    a = ev.Lattice(2, 96, 40, 1, storage="f32")
+    b = ev.Lattice(2, 96, 40, 1, storage="f32")
+    for L in (a, b):
+        L.set_params(**P)
+        L.init_fields(rho, T)
+    b.set_option(ev.OPT_USE_GRAPH, 0)
+    for n in (70, 5, 64, 33):
+        a.step(n)
+        b.step(n)
+    fa, ga = a.get_populations()
+    fb, gb = b.get_populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    assert a.step_count == b.step_count == 172
