@@ -140,6 +140,7 @@ def main():
     achieved = alg_bytes / (t_col * 1e-3) / 1e9
     step_eff = alg_bytes / (ms * 1e-3) / 1e9
     traffic = hbm_traffic("k_collide", f"d3q27_{n}_f32")
+    copy_gbs = ev.copy_probe(4e9, 20)
     sums = L.global_sums()
     result = {
         "metric": "MLUPS (D3Q27 256^3 FP32 lattice updates per second) and HBM GB/s",
@@ -163,7 +164,8 @@ def main():
                      "kernel": "k_collide",
                      "kernel_ms": round(t_col, 4), "moments_kernel_ms": round(t_mom, 4),
                      "alg_bytes_per_launch": alg_bytes,
-                     "step_effective_GBps": round(step_eff, 1)},
+                     "step_effective_GBps": round(step_eff, 1),
+                     "copy_probe_GBps": round(copy_gbs, 1)},
         "mass": sums[0],
     }
     del L

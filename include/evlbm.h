@@ -153,6 +153,13 @@ int evlbm_synchronize(evlbm_t h);
  * initial profiles.  Errors: EINVAL if T is not below T_c = 8a/(27 b R). */
 int evlbm_eos_coexistence(double R, double a, double b, double T, double out[3]);
 
+/* Attainable HBM bandwidth: a plain device-to-device streaming copy of
+ * `bytes` total traffic (half read, half written), timed over `reps` launches
+ * with HIP events on the default stream.  Context for the roofline figures
+ * and the reference for byte-counter calibration.  Blocks.
+ * Errors: EINVAL, ENOMEM, EHIP. */
+int evlbm_copy_probe(double bytes, int reps, double *gbps_out);
+
 /* Build information: "gfx950 <storage variants> <date>" (static string). */
 const char *evlbm_version(void);
 

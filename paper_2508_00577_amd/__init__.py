@@ -69,6 +69,7 @@ def lib():
         L.evlbm_synchronize.argtypes = [_vp]
         L.evlbm_profile_step.argtypes = [_vp, ctypes.c_int, _dp]
         L.evlbm_eos_coexistence.argtypes = [ctypes.c_double] * 4 + [_dp]
+        L.evlbm_copy_probe.argtypes = [ctypes.c_double, ctypes.c_int, _dp]
         _lib = L
     return _lib
 
@@ -95,6 +96,13 @@ def eos_coexistence(T, R=1.0, a=0.0225, b=1.0 / 3.0):
     out = np.zeros(3)
     _check(lib().evlbm_eos_coexistence(R, a, b, T, out.ctypes.data_as(_dp)))
     return tuple(out)
+
+
+def copy_probe(bytes_total=4e9, reps=20):
+    """GB/s of a plain streaming copy moving bytes_total per launch (read + write)."""
+    out = ctypes.c_double()
+    _check(lib().evlbm_copy_probe(float(bytes_total), int(reps), ctypes.byref(out)))
+    return out.value
 
 
 def version():
@@ -196,6 +204,8 @@ class Lattice:
             T = torch.empty(self.shape, dtype=dtype, device="cuda")
         where = DEVICE_F64 if dtype == torch.float64 else DEVICE_F32
         _check(lib().evlbm_read_moments(self._h, _ptr(rho), _ptr(u), _ptr(T), where))
+        # the readout is enqueued on the lattice's stream: order the caller's stream after it
+        torch.cuda.current_stream().wait_stream(self.stream)
         return rho, u, T
 
     def global_sums(self):

@@ -115,11 +115,22 @@ struct Ops {
         hipLaunchKernelGGL((k_moments<D, S>), row_grid(h, bx), dim3(bx), 0, h->stream, (const T *)pop, (R *)h->m,
                            make_params<R>(h));
     }
+    // z-marching tile of the D3Q27 kernel: TX x TY columns, ZC planes per chunk
+    static constexpr int TX = (S == EVLBM_F64) ? 16 : 32;
+    static constexpr int TY = 8;
+    static constexpr int ZC = 32;
+
     static void collide(evlbm_lattice *h, const void *src, void *dst)
     {
-        dim3 grid((h->nx + BX - 1) / BX, (h->ny + BY - 1) / BY, (h->nz + BZ - 1) / BZ);
-        hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ>), grid, dim3(BX, BY, BZ), 0, h->stream, (const T *)src,
-                           (T *)dst, (const R *)h->m, make_params<R>(h));
+        if (D == 3) {
+            dim3 grid((h->nx + TX - 1) / TX, (h->ny + TY - 1) / TY, (h->nz + ZC - 1) / ZC);
+            hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC>), grid, dim3(TX, TY), 0, h->stream, (const T *)src,
+                               (T *)dst, (const R *)h->m, make_params<R>(h));
+        } else {
+            dim3 grid((h->nx + BX - 1) / BX, (h->ny + BY - 1) / BY, (h->nz + BZ - 1) / BZ);
+            hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ>), grid, dim3(BX, BY, BZ), 0, h->stream, (const T *)src,
+                               (T *)dst, (const R *)h->m, make_params<R>(h));
+        }
     }
     static void init(evlbm_lattice *h, const double *rho, const double *u, const double *T0)
     {
@@ -857,3 +868,48 @@ int evlbm_eos_coexistence(double R, double a, double b, double T, double out[3])
 
 }  // extern "C"
 
+
+// ------------------------------------------------------------ copy probe
+
+namespace evlbm {
+// Plain streaming copy, 16 bytes per thread per iteration, grid-stride.
+__global__ void __launch_bounds__(256) k_copy_probe(const float4 *__restrict__ in, float4 *__restrict__ out, long n)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) out[t] = in[t];
+}
+}  // namespace evlbm
+
+extern "C" int evlbm_copy_probe(double bytes, int reps, double *gbps_out)
+{
+    if (!gbps_out || !(bytes >= 1024) || reps <= 0) return fail(EVLBM_EINVAL, "need bytes >= 1024 and reps > 0");
+    const long n = (long)(bytes / 2 / sizeof(float4));  // half read, half written
+    float4 *a = nullptr, *b = nullptr;
+    hipError_t e = hipMalloc(&a, n * sizeof(float4));
+    if (e == hipSuccess) e = hipMalloc(&b, n * sizeof(float4));
+    if (e != hipSuccess) {
+        if (a) (void)hipFree(a);
+        return fail(EVLBM_ENOMEM, "copy probe allocation: %s", hipGetErrorString(e));
+    }
+    (void)hipMemset(a, 0, n * sizeof(float4));
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
+    const int blocks = cus * 8;
+    hipEvent_t t0, t1;
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    hipLaunchKernelGGL(k_copy_probe, dim3(blocks), dim3(256), 0, nullptr, a, b, n);
+    (void)hipEventRecord(t0, nullptr);
+    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_copy_probe, dim3(blocks), dim3(256), 0, nullptr, a, b, n);
+    (void)hipEventRecord(t1, nullptr);
+    e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (e != hipSuccess) return hip_fail(e, "copy probe");
+    *gbps_out = 2.0 * n * sizeof(float4) * reps / (ms * 1e-3) / 1e9;
+    return EVLBM_OK;
+}

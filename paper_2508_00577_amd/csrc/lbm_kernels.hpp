@@ -104,6 +104,101 @@ __global__ void __launch_bounds__(256) k_moments(const StoreT<S> *__restrict__ p
     m[(D + 1) * p.N + cell] = e;
 }
 
+// Equilibria (eq. feq, f_star, geq, gstar with eq. g_corr), shifted state
+// (eq. def_ustar with Qtilde = 0) and the update eq. pre_LBM for one cell,
+// pulling f, g from src and storing into dst.
+template <int D, int S>
+__device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
+                                    const StepParams<RealT<S>> &p, int x, int y, int z, RealT<S> rho,
+                                    RealT<S> inv_rho, RealT<S> K, RealT<S> RT, RealT<S> one_m_br, RealT<S> theta,
+                                    const RealT<S> u[3], const RealT<S> F[3], const RealT<S> Phi[3],
+                                    const RealT<S> qp[3])
+{
+    using R = RealT<S>;
+    constexpr int Q = Lat<D>::Q;
+    const long N = p.N;
+    (void)RT;
+    // shifted state (eq. def_ustar, Qtilde = 0)
+    R us[3], F2 = R(0);
+    for (int a = 0; a < 3; ++a) {
+        us[a] = u[a] + p.lambda * F[a] * inv_rho;
+        F2 += F[a] * F[a];
+    }
+    // (3/2) RT* = (3/2) RT - lambda^2 |F|^2/(2 rho^2)
+    const R hS = K - R(0.5) * p.lambda * p.lambda * F2 * inv_rho * inv_rho;
+    const R RTs = hS * (R(2) / R(3));
+    const R thetas = RTs / one_m_br;
+
+    // per-axis factors: fe (f^eq and g^eq), fs (f*), gs (g*), chi for g^eq, g*
+    R fe[3][3], fs[3][3], gs[3][3], xe[3][3], xs[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (a < D) {
+            psi3<R>(u[a], theta + u[a] * u[a], fe[a]);
+            psi3<R>(us[a], theta + us[a] * us[a] + p.lambda * Phi[a] * inv_rho, fs[a]);
+            psi3<R>(us[a], thetas + us[a] * us[a], gs[a]);
+            chi3<R>(u[a], theta, xe[a]);
+            chi3<R>(us[a], thetas, xs[a]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                fe[a][k] = fs[a][k] = gs[a][k] = (k == 1) ? R(1) : R(0);
+                xe[a][k] = xs[a][k] = R(0);
+            }
+        }
+    }
+    const R hE = K;
+    const R omb = R(1) - p.two_beta;
+    const R c_eq = p.two_beta - p.wstar;
+
+    const int xs_[3] = {x + 1 == p.nx ? 0 : x + 1, x, x == 0 ? p.nx - 1 : x - 1};
+    const int ys_[3] = {y + 1 == p.ny ? 0 : y + 1, y, y == 0 ? p.ny - 1 : y - 1};
+    const int zs_[3] = {z + 1 == p.nz ? 0 : z + 1, z, z == 0 ? p.nz - 1 : z - 1};
+    const long cell = (long)x + (long)p.nx * ((long)y + (long)p.ny * z);
+
+    // The collision conserves mass and energy exactly: sum f_new = sum fh and
+    // sum g_new = sum gh + u.F (eq. pre_LBM with eq. u_shift, T_shift and
+    // Qtilde = 0).  The rest direction is stored last, as the exact (FP64)
+    // incoming sum minus the exact sum of the values actually stored in the
+    // other directions, so each cell keeps these balances to a single rounding
+    // of one stored value and no rounding bias accumulates from step to step.
+    constexpr int REST = (Q - 1) / 2;
+    const R fh_rest = Codec<S>::dec(src[(long)REST * N + cell], p.ref[REST]);
+    const R gh_rest = Codec<S>::dec(src[(long)(Q + REST) * N + cell], p.ref[Q + REST]);
+    double mass = (double)fh_rest, energy = (double)gh_rest, sf = 0.0, sg = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (i == REST) continue;
+        const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
+        const long s = (long)xs_[kx] + (long)p.nx * ((long)ys_[ky] + (long)p.ny * zs_[kz]);
+        const R fh = Codec<S>::dec(src[(long)i * N + s], p.ref[i]);
+        const R gh = Codec<S>::dec(src[(long)(Q + i) * N + s], p.ref[Q + i]);
+        const R Pyz_e = fe[1][ky] * fe[2][kz];
+        const R feq = rho * fe[0][kx] * Pyz_e;
+        const R fst = rho * fs[0][kx] * (fs[1][ky] * fs[2][kz]);
+        const R geq = rho * ((hE * fe[0][kx] + xe[0][kx]) * Pyz_e +
+                             fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
+        R gst = rho * ((hS * gs[0][kx] + xs[0][kx]) * (gs[1][ky] * gs[2][kz]) +
+                       gs[0][kx] * (xs[1][ky] * gs[2][kz] + gs[1][ky] * xs[2][kz]));
+        if (cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_d<D>(i) * cz_d<D>(i) == 1)
+            gst += R(0.5) * (R(cx_of(i)) * qp[0] + R(cy_of(i)) * qp[1] + R(cz_d<D>(i)) * qp[2]);
+        // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq)
+        const R fn = omb * fh + c_eq * feq + p.wstar * fst;
+        const R gn = omb * gh + c_eq * geq + p.wstar * gst;
+        const StoreT<S> fq = Codec<S>::enc(fn, p.ref[i]);
+        const StoreT<S> gq = Codec<S>::enc(gn, p.ref[Q + i]);
+        dst[(long)i * N + cell] = fq;
+        dst[(long)(Q + i) * N + cell] = gq;
+        mass += (double)fh;
+        energy += (double)gh;
+        sf += (double)Codec<S>::dec(fq, p.ref[i]);
+        sg += (double)Codec<S>::dec(gq, p.ref[Q + i]);
+    }
+    const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
+    dst[(long)REST * N + cell] = Codec<S>::enc((R)(mass - sf), p.ref[REST]);
+    dst[(long)(Q + REST) * N + cell] = Codec<S>::enc((R)(energy + uF - sg), p.ref[Q + REST]);
+}
+
 // ------------------------------------------------------------ k_collide
 
 template <int D, int BX, int BY, int BZ>
@@ -228,85 +323,245 @@ __global__ void __launch_bounds__(BX *BY *BZ)
         Phi[2] = p.sphi * lds_grad<D, 2, R>(s_f1 + (F_M + 2) * TS::N1, c1, SY, SZ) + Phip;
         qp[2] = p.lambda * (P0 * lds_grad<D, 2, R>(s_f1 + F_TD * TS::N1, c1, SY, SZ) + u[2] * Phip);
     }
-    // shifted state (eq. def_ustar, Qtilde = 0)
-    R us[3], F2 = R(0);
-    for (int a = 0; a < 3; ++a) {
-        us[a] = u[a] + p.lambda * F[a] * inv_rho;
-        F2 += F[a] * F[a];
-    }
-    // (3/2) RT* = (3/2) RT - lambda^2 |F|^2/(2 rho^2)
-    const R hS = K - R(0.5) * p.lambda * p.lambda * F2 * inv_rho * inv_rho;
-    const R RTs = hS * (R(2) / R(3));
-    const R thetas = RTs / one_m_br;
+    collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, one_m_br, theta, u, F, Phi, qp);
+}
 
-    // per-axis factors: fe (f^eq and g^eq), fs (f*), gs (g*), chi for g^eq, g*
-    R fe[3][3], fs[3][3], gs[3][3], xe[3][3], xs[3][3];
+// ------------------------------------------------------- k_collide_zm (3D)
+
+// D3Q27 variant that marches along z: a workgroup owns a TX x TY column of
+// cells and walks a chunk of ZC planes, keeping the per-plane inputs of the
+// stencil chain in LDS ring buffers, so the radius-3 halo is recomputed only
+// in x and y.  At iteration k it loads rho of plane k+3 (tile + 3), forms
+// lap rho of plane k+2 (tile + 2), the force and half-step fields of plane
+// k+1 (tile + 1) and collides plane k.  Ring depths: rho 5 planes (k..k+3 are
+// read while a fast wave may already write k+4), lap 3, fields 3; the writes
+// of iteration k+1 into slots still read in iteration k happen after that
+// iteration's first barrier.
+template <int TX, int TY>
+struct ZTile {
+    static constexpr int R3X = TX + 6, R3Y = TY + 6, N3 = R3X * R3Y;
+    static constexpr int R2X = TX + 4, R2Y = TY + 4, N2 = R2X * R2Y;
+    static constexpr int R1X = TX + 2, R1Y = TY + 2, N1 = R1X * R1Y;
+    static constexpr int NT = TX * TY;
+    static constexpr int NRHO = 5, NLAP = 3, NFLD = 3;  // ring depths (planes)
+    static constexpr int NF = 7;  // u (3), M (3), theta - RT
+};
+
+// Isotropic derivative along axis A at in-plane offset c of three planes
+// (below, centre, above) with row stride sy.
+template <int A, typename R>
+__device__ inline R ring_grad(const R *pm, const R *p0, const R *pp, int c, int sy)
+{
+    const R *pl[3] = {pm, p0, pp};
+    R acc = R(0);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (a < D) {
-            psi3<R>(u[a], theta + u[a] * u[a], fe[a]);
-            psi3<R>(us[a], theta + us[a] * us[a] + p.lambda * Phi[a] * inv_rho, fs[a]);
-            psi3<R>(us[a], thetas + us[a] * us[a], gs[a]);
-            chi3<R>(u[a], theta, xe[a]);
-            chi3<R>(us[a], thetas, xs[a]);
-        } else {
+    for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                fe[a][k] = fs[a][k] = gs[a][k] = (k == 1) ? R(1) : R(0);
-                xe[a][k] = xs[a][k] = R(0);
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int ca = (A == 0) ? dx : (A == 1) ? dy : dz;
+                if (ca == 0) continue;
+                const R w = R(3) * w1<R>(dx) * w1<R>(dy) * w1<R>(dz) * R(ca);
+                acc += w * pl[dz + 1][c + dx + dy * sy];
+            }
+    return acc;
+}
+
+template <int A, typename R>
+__device__ inline R ring_grad_sq(const R *pm, const R *p0, const R *pp, int c, int sy)
+{
+    const R *pl[3] = {pm, p0, pp};
+    R acc = R(0);
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int ca = (A == 0) ? dx : (A == 1) ? dy : dz;
+                if (ca == 0) continue;
+                const R w = R(3) * w1<R>(dx) * w1<R>(dy) * w1<R>(dz) * R(ca);
+                const R v = pl[dz + 1][c + dx + dy * sy];
+                acc += w * (v * v);
+            }
+    return acc;
+}
+
+template <typename R>
+__device__ inline R ring_lap(const R *pm, const R *p0, const R *pp, int c, int sy)
+{
+    const R *pl[3] = {pm, p0, pp};
+    const R centre = p0[c];
+    R acc = R(0);
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0 && dz == 0) continue;
+                const R w = R(6) * w1<R>(dx) * w1<R>(dy) * w1<R>(dz);
+                acc += w * (pl[dz + 1][c + dx + dy * sy] - centre);
+            }
+    return acc;
+}
+
+__device__ inline int ring_slot(int k, int n) { return (k + 8 * n) % n; }
+
+template <int S, int TX, int TY, int ZC>
+__global__ void __launch_bounds__(TX *TY)
+    k_collide_zm(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
+                 StepParams<RealT<S>> p)
+{
+    using R = RealT<S>;
+    using ZT = ZTile<TX, TY>;
+    constexpr int Q = 27;
+    constexpr int D = 3;
+    constexpr int FU = 0, FM = 3, FTD = 6;
+    __shared__ R s_rho[ZT::NRHO][ZT::N3];
+    __shared__ R s_lap[ZT::NLAP][ZT::N2];
+    __shared__ R s_fld[ZT::NFLD][ZT::NF][ZT::N1];
+
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = tx + TX * ty;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int z0 = blockIdx.z * ZC;
+    const int z1 = min(z0 + ZC, p.nz);
+    const long N = p.N;
+    const long plane = (long)p.nx * p.ny;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < p.nx && y < p.ny;
+    // F and K = (3/2) RT of this thread's own column at planes k (cur) and k+1 (nxt)
+    R Fc[3] = {R(0), R(0), R(0)}, Kc = R(0), Fn[3] = {R(0), R(0), R(0)}, Kn = R(0);
+
+    // Collision of plane z0 needs the fields of planes z0-1..z0+1, hence lap
+    // rho of z0-2..z0+2 and rho of z0-3..z0+3: the pipeline starts 6 planes early.
+    for (int k = z0 - 6; k < z1; ++k) {
+        // (1) rho of plane k + 3 on tile + 3
+        {
+            const int zz = wrapi(k + 3, p.nz);
+            R *dstp = s_rho[ring_slot(k + 3, ZT::NRHO)];
+            for (int t = tid; t < ZT::N3; t += ZT::NT) {
+                const int lx = t % ZT::R3X, ly = t / ZT::R3X;
+                const int gx = wrapi(x0 + lx - 3, p.nx), gy = wrapi(y0 + ly - 3, p.ny);
+                dstp[t] = m[(long)gx + (long)p.nx * gy + plane * zz];
             }
         }
-    }
-    const R hE = K;
-    const R omb = R(1) - p.two_beta;
-    const R c_eq = p.two_beta - p.wstar;
-
-    const int xs_[3] = {x + 1 == p.nx ? 0 : x + 1, x, x == 0 ? p.nx - 1 : x - 1};
-    const int ys_[3] = {y + 1 == p.ny ? 0 : y + 1, y, y == 0 ? p.ny - 1 : y - 1};
-    const int zs_[3] = {z + 1 == p.nz ? 0 : z + 1, z, z == 0 ? p.nz - 1 : z - 1};
-    const long cell = (long)x + (long)p.nx * ((long)y + (long)p.ny * z);
-
-    // The collision conserves mass and energy exactly: sum f_new = sum fh and
-    // sum g_new = sum gh + u.F (eq. pre_LBM with eq. u_shift, T_shift and
-    // Qtilde = 0).  The rest direction is stored last, as the exact (FP64)
-    // incoming sum minus the exact sum of the values actually stored in the
-    // other directions, so each cell keeps these balances to a single rounding
-    // of one stored value and no rounding bias accumulates from step to step.
-    constexpr int REST = (Q - 1) / 2;
-    const R fh_rest = Codec<S>::dec(src[(long)REST * N + cell], p.ref[REST]);
-    const R gh_rest = Codec<S>::dec(src[(long)(Q + REST) * N + cell], p.ref[Q + REST]);
-    double mass = (double)fh_rest, energy = (double)gh_rest, sf = 0.0, sg = 0.0;
+        __syncthreads();
+        // (2) lap rho of plane k + 2 on tile + 2
+        {
+            const R *a = s_rho[ring_slot(k + 1, ZT::NRHO)], *b = s_rho[ring_slot(k + 2, ZT::NRHO)],
+                    *c = s_rho[ring_slot(k + 3, ZT::NRHO)];
+            R *dstp = s_lap[ring_slot(k + 2, ZT::NLAP)];
+            for (int t = tid; t < ZT::N2; t += ZT::NT) {
+                const int lx = t % ZT::R2X, ly = t / ZT::R2X;
+                dstp[t] = ring_lap<R>(a, b, c, (lx + 1) + ZT::R3X * (ly + 1), ZT::R3X);
+            }
+        }
+        __syncthreads();
+        // (3) force and half-step fields of plane k + 1 on tile + 1
+        {
+            const int zz = wrapi(k + 1, p.nz);
+            const R *ra = s_rho[ring_slot(k, ZT::NRHO)], *rb = s_rho[ring_slot(k + 1, ZT::NRHO)],
+                    *rc = s_rho[ring_slot(k + 2, ZT::NRHO)];
+            const R *la = s_lap[ring_slot(k, ZT::NLAP)], *lb = s_lap[ring_slot(k + 1, ZT::NLAP)],
+                    *lc = s_lap[ring_slot(k + 2, ZT::NLAP)];
+            R(*fd)[ZT::N1] = s_fld[ring_slot(k + 1, ZT::NFLD)];
+            // interior cells first (thread tid owns cell (tx, ty)), then the ring
+            for (int t = tid; t < ZT::N1; t += ZT::NT) {
+                int lx, ly;
+                if (t < ZT::NT) {
+                    lx = t % TX + 1;
+                    ly = t / TX + 1;
+                } else {
+                    const int r = t - ZT::NT;  // ring cells: rows 0 and R1Y-1, then columns 0 and R1X-1
+                    if (r < 2 * ZT::R1X) {
+                        lx = r % ZT::R1X;
+                        ly = (r < ZT::R1X) ? 0 : ZT::R1Y - 1;
+                    } else {
+                        const int q = r - 2 * ZT::R1X;
+                        lx = (q < TY) ? 0 : ZT::R1X - 1;
+                        ly = q % TY + 1;
+                    }
+                }
+                const int c3 = (lx + 2) + ZT::R3X * (ly + 2);
+                const int c2 = (lx + 1) + ZT::R2X * (ly + 1);
+                const R rho = rb[c3];
+                R F[3];
+                F[0] = p.a * ring_grad_sq<0, R>(ra, rb, rc, c3, ZT::R3X) + p.kappa * rho * ring_grad<0, R>(la, lb, lc, c2, ZT::R2X);
+                F[1] = p.a * ring_grad_sq<1, R>(ra, rb, rc, c3, ZT::R3X) + p.kappa * rho * ring_grad<1, R>(la, lb, lc, c2, ZT::R2X);
+                F[2] = p.a * ring_grad_sq<2, R>(ra, rb, rc, c3, ZT::R3X) + p.kappa * rho * ring_grad<2, R>(la, lb, lc, c2, ZT::R2X);
+                const int gx = wrapi(x0 + lx - 1, p.nx), gy = wrapi(y0 + ly - 1, p.ny);
+                const long cell = (long)gx + (long)p.nx * gy + plane * zz;
+                R u[3], uF = R(0), u2 = R(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (i == REST) continue;
-        const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
-        const long s = (long)xs_[kx] + (long)p.nx * ((long)ys_[ky] + (long)p.ny * zs_[kz]);
-        const R fh = Codec<S>::dec(src[(long)i * N + s], p.ref[i]);
-        const R gh = Codec<S>::dec(src[(long)(Q + i) * N + s], p.ref[Q + i]);
-        const R Pyz_e = fe[1][ky] * fe[2][kz];
-        const R feq = rho * fe[0][kx] * Pyz_e;
-        const R fst = rho * fs[0][kx] * (fs[1][ky] * fs[2][kz]);
-        const R geq = rho * ((hE * fe[0][kx] + xe[0][kx]) * Pyz_e +
-                             fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
-        R gst = rho * ((hS * gs[0][kx] + xs[0][kx]) * (gs[1][ky] * gs[2][kz]) +
-                       gs[0][kx] * (xs[1][ky] * gs[2][kz] + gs[1][ky] * xs[2][kz]));
-        if (cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_d<D>(i) * cz_d<D>(i) == 1)
-            gst += R(0.5) * (R(cx_of(i)) * qp[0] + R(cy_of(i)) * qp[1] + R(cz_d<D>(i)) * qp[2]);
-        // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq)
-        const R fn = omb * fh + c_eq * feq + p.wstar * fst;
-        const R gn = omb * gh + c_eq * geq + p.wstar * gst;
-        const StoreT<S> fq = Codec<S>::enc(fn, p.ref[i]);
-        const StoreT<S> gq = Codec<S>::enc(gn, p.ref[Q + i]);
-        dst[(long)i * N + cell] = fq;
-        dst[(long)(Q + i) * N + cell] = gq;
-        mass += (double)fh;
-        energy += (double)gh;
-        sf += (double)Codec<S>::dec(fq, p.ref[i]);
-        sg += (double)Codec<S>::dec(gq, p.ref[Q + i]);
+                for (int a = 0; a < 3; ++a) {
+                    u[a] = (m[(a + 1) * N + cell] + R(0.5) * F[a]) / rho;
+                    uF += u[a] * F[a];
+                    u2 += u[a] * u[a];
+                }
+                const R K = (m[4 * N + cell] + R(0.5) * uF) / rho - R(0.5) * u2;
+                const R RT = K * (R(2) / R(3));
+                const R theta = RT / (R(1) - p.b * rho);
+                const int c1 = lx + ZT::R1X * ly;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    fd[FU + a][c1] = u[a];
+                    fd[FM + a][c1] = rho * u[a] * (u[a] * u[a] + R(3) * theta - R(1));
+                }
+                fd[FTD][c1] = theta - RT;
+                if (t < ZT::NT) {
+                    Fn[0] = F[0];
+                    Fn[1] = F[1];
+                    Fn[2] = F[2];
+                    Kn = K;
+                }
+            }
+        }
+        __syncthreads();
+        // (4) collide plane k
+        if (k >= z0 && active) {
+            const int z = k;
+            const R *fm[ZT::NF], *f0[ZT::NF], *fp[ZT::NF];
+#pragma unroll
+            for (int q = 0; q < ZT::NF; ++q) {
+                fm[q] = s_fld[ring_slot(k - 1, ZT::NFLD)][q];
+                f0[q] = s_fld[ring_slot(k, ZT::NFLD)][q];
+                fp[q] = s_fld[ring_slot(k + 1, ZT::NFLD)][q];
+            }
+            const int c1 = (tx + 1) + ZT::R1X * (ty + 1);
+            const R rho = s_rho[ring_slot(k, ZT::NRHO)][(tx + 3) + ZT::R3X * (ty + 3)];
+            const R inv_rho = R(1) / rho;
+            const R K = Kc;
+            const R RT = K * (R(2) / R(3));
+            const R one_m_br = R(1) - p.b * rho;
+            const R theta = RT / one_m_br;
+            const R P0 = rho * theta;
+            R u[3], F[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                u[a] = f0[FU + a][c1];
+                F[a] = Fc[a];
+            }
+            const R divu = ring_grad<0, R>(fm[FU], f0[FU], fp[FU], c1, ZT::R1X) +
+                           ring_grad<1, R>(fm[FU + 1], f0[FU + 1], fp[FU + 1], c1, ZT::R1X) +
+                           ring_grad<2, R>(fm[FU + 2], f0[FU + 2], fp[FU + 2], c1, ZT::R1X);
+            const R Phip = P0 * (R(5) / R(3)) * (R(1) - R(1) / one_m_br) * divu;
+            R Phi[3], qp[3];
+            Phi[0] = p.sphi * ring_grad<0, R>(fm[FM], f0[FM], fp[FM], c1, ZT::R1X) + Phip;
+            Phi[1] = p.sphi * ring_grad<1, R>(fm[FM + 1], f0[FM + 1], fp[FM + 1], c1, ZT::R1X) + Phip;
+            Phi[2] = p.sphi * ring_grad<2, R>(fm[FM + 2], f0[FM + 2], fp[FM + 2], c1, ZT::R1X) + Phip;
+            qp[0] = p.lambda * (P0 * ring_grad<0, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[0] * Phip);
+            qp[1] = p.lambda * (P0 * ring_grad<1, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[1] * Phip);
+            qp[2] = p.lambda * (P0 * ring_grad<2, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[2] * Phip);
+            collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, one_m_br, theta, u, F, Phi, qp);
+        }
+        // rotate the column's F, K
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Fc[a] = Fn[a];
+        Kc = Kn;
     }
-    const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
-    dst[(long)REST * N + cell] = Codec<S>::enc((R)(mass - sf), p.ref[REST]);
-    dst[(long)(Q + REST) * N + cell] = Codec<S>::enc((R)(energy + uF - sg), p.ref[Q + REST]);
 }
 
 // ------------------------------------------------------------ readout

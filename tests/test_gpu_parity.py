@@ -197,3 +197,35 @@ def test_graph_replay_matches_eager():
     fb, gb = b.get_populations()
     assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
     assert a.step_count == b.step_count == 172
+
+
+@pytest.mark.parametrize("shape,steps", [((70, 12, 20), 20), ((1, 9, 17), 30), ((2, 5, 6), 30)])
+def test_3d_z_chunks_and_thin_lattices(shape, steps):
+    """D3Q27 with several z-chunks (one ragged), a single plane, and tiny sizes
+    where the halo wraps more than once."""
+    rho, T = _state("droplet", shape, 0.85, 1e-3)
+    g, o = _pair(3, shape, "f64", rho, T)
+    g.step(steps)
+    o.step(steps)
+    _compare(g, o, 1e-11, f"3d {shape} f64 step {steps}")
+
+
+@pytest.mark.parametrize("D,shape,storage", [(2, (1, 40, 96), "f16dev"), (2, (1, 40, 96), "bf16dev"),
+                                             (3, (24, 20, 36), "f16dev"), (3, (24, 20, 36), "bf16dev")])
+def test_16bit_deviation_storage_tracks_fp32(D, shape, storage):
+    """Populations stored as 16-bit deviations from a reference equilibrium,
+    FP32 arithmetic: density within 1e-3 (relative) of the FP32-storage run."""
+    rho, T = _state("droplet", shape, 0.8, 1e-4)
+    nz, ny, nx = shape
+    runs = {}
+    for st in ("f32", storage):
+        L = ev.Lattice(D, nx, ny, nz, storage=st)
+        L.set_params(**P)
+        L.set_option(ev.OPT_REF_RHO, float(rho.mean()))
+        L.set_option(ev.OPT_REF_T, float(T.mean()))
+        L.init_fields(rho, T)
+        L.step(300)
+        runs[st] = L.moments()
+    e = _errs(runs[storage], runs["f32"])
+    print(f"{storage} D={D}: e_rho={e[0]:.2e} e_u={e[1]:.2e} e_T={e[2]:.2e}", flush=True)
+    assert e[0] < 1e-3
