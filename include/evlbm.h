@@ -45,9 +45,12 @@ enum {
 
 enum { EVLBM_D2Q9 = 2, EVLBM_D3Q27 = 3 };
 
-/* Population storage.  F16DEV/BF16DEV store h_i = f_i - f_i^ref in 16 bits,
- * f^ref the equilibrium of a uniform reference state at rest (options
- * EVLBM_OPT_REF_RHO, EVLBM_OPT_REF_T), decoded to FP32 for the arithmetic. */
+/* Population storage.  F16DEV/BF16DEV store h_i(x) = f_i(x) - rho_ref(x) W_i
+ * in 16 bits (round to nearest even) and decode to FP32 for the arithmetic:
+ * W_i is the equilibrium at rest per unit density at the reference state
+ * (options EVLBM_OPT_REF_RHO, EVLBM_OPT_REF_T) and rho_ref(x) a per-cell
+ * reference density, set to the initial density field (or to the stored
+ * density of every cell by a re-reference, EVLBM_OPT_REREF_EVERY). */
 enum { EVLBM_F64 = 0, EVLBM_F32 = 1, EVLBM_F16DEV = 2, EVLBM_BF16DEV = 3 };
 
 enum { EVLBM_HOST_F64 = 0, EVLBM_DEVICE_F32 = 1, EVLBM_DEVICE_F64 = 2 };
@@ -57,7 +60,8 @@ enum {
     EVLBM_OPT_REF_RHO = 2,     /* reference density of the 16-bit deviation storage */
     EVLBM_OPT_REF_T = 3,       /* reference temperature of the 16-bit deviation storage */
     EVLBM_OPT_CHECK_EVERY = 4, /* scan for non-finite densities every K steps (0 = never) */
-    EVLBM_OPT_USE_GRAPH = 5    /* 1: replay step chunks from a captured hipGraph (default 1) */
+    EVLBM_OPT_USE_GRAPH = 5,   /* 1: replay step chunks from a captured hipGraph (default 1) */
+    EVLBM_OPT_REREF_EVERY = 6  /* 16-bit storage: re-reference every K steps (0 = never) */
 };
 
 enum { EVLBM_MEASURE_SLAB = 1, EVLBM_MEASURE_DROPLET = 2 };

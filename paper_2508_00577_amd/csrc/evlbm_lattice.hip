@@ -2,6 +2,7 @@
 // cycle, parameters, initialisation, time stepping, readout, reductions,
 // population I/O and checkpoints.
 #include <cmath>
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -84,11 +85,16 @@ StepParams<R> make_params(const evlbm_lattice *h)
     p.sphi = (R)h->sphi;
     p.Rgas = (R)h->R;
     double ref[54];
-    if (h->storage == EVLBM_F16DEV || h->storage == EVLBM_BF16DEV)
+    if (h->storage == EVLBM_F16DEV || h->storage == EVLBM_BF16DEV) {
+        // per unit density: the equilibrium at rest is proportional to rho
+        // at fixed theta and RT
         reference_populations(h->D, h->R, h->b, h->ref_rho, h->ref_T, ref);
-    else
+        for (int i = 0; i < 54; ++i) ref[i] /= h->ref_rho;
+    } else {
         for (int i = 0; i < 54; ++i) ref[i] = 0.0;
+    }
     for (int i = 0; i < 54; ++i) p.ref[i] = (R)ref[i];
+    p.refrho = h->refrho;
     return p;
 }
 
@@ -325,6 +331,24 @@ void launch_step(evlbm_lattice *h)
     h->step++;
 }
 
+// 16-bit deviation storage: decode with the current per-cell reference, take
+// the stored density of every cell as the new reference and encode again.
+int rereference(evlbm_lattice *h)
+{
+    if (!h->refrho) return EVLBM_OK;
+    const size_t half = sizeof(double) * h->N * h->Q;
+    int rc = ensure_scratch(h, 2 * half);
+    if (rc) return rc;
+    dispatch<RunDecode>(h, (double *)h->scratch);
+    hipLaunchKernelGGL(k_refrho_from_pops, dim3((h->N + 255) / 256), dim3(256), 0, h->stream,
+                       (const double *)h->scratch, h->N, h->Q, h->refrho);
+    dispatch<RunEncode>(h, (const double *)h->scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "re-reference");
+    h->m_valid = false;
+    return EVLBM_OK;
+}
+
 // Steps are replayed from a captured graph of GRAPH_STEPS launches pairs
 // (an even count, so the buffer parity is unchanged), one graph per parity.
 static constexpr int GRAPH_STEPS = 32;
@@ -407,6 +431,8 @@ int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream,
     }
     e = hipMalloc(&h->m, m_bytes);
     if (e == hipSuccess) e = hipMalloc(&h->lap, (size_t)h->N * real_bytes(storage));
+    if (e == hipSuccess && (storage == EVLBM_F16DEV || storage == EVLBM_BF16DEV))
+        e = hipMalloc(&h->refrho, (size_t)h->N * sizeof(float));
     if (e != hipSuccess) {
         evlbm_destroy(h);
         return fail(EVLBM_ENOMEM, "hipMalloc for moment fields: %s", hipGetErrorString(e));
@@ -424,6 +450,7 @@ int evlbm_destroy(evlbm_t h)
         if (h->buf[k]) hipFree(h->buf[k]);
     if (h->m) hipFree(h->m);
     if (h->lap) hipFree(h->lap);
+    if (h->refrho) hipFree(h->refrho);
     if (h->scratch) hipFree(h->scratch);
     delete h;
     return EVLBM_OK;
@@ -486,6 +513,10 @@ int evlbm_set_option(evlbm_t h, int key, double value)
     case EVLBM_OPT_USE_GRAPH:
         h->use_graph = value != 0.0;
         break;
+    case EVLBM_OPT_REREF_EVERY:
+        if (value < 0) return fail(EVLBM_EINVAL, "re-reference period must be >= 0");
+        h->reref_every = (int64_t)value;
+        break;
     default:
         return fail(EVLBM_EINVAL, "unknown option %d", key);
     }
@@ -546,6 +577,9 @@ int evlbm_init_fields(evlbm_t h, const void *rho, const void *u, const void *T, 
         if (host & 1) return fail(EVLBM_ENONPHYS, "need rho > 0, b rho < 1, T > 0 everywhere");
     }
     h->cur = 0;
+    if (h->refrho)
+        hipLaunchKernelGGL(k_f64_to_f32, dim3((N + 255) / 256), dim3(256), 0, h->stream, (const double *)d_rho,
+                           h->refrho, N);
     dispatch<RunInit>(h, (const double *)d_rho, (const double *)d_u, (const double *)d_T);
     rc = check_launch("k_init");
     if (rc) return rc;
@@ -565,17 +599,20 @@ int evlbm_step(evlbm_t h, int64_t nsteps)
     if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
     if (nsteps < 0) return fail(EVLBM_EINVAL, "nsteps must be >= 0");
     int64_t done = 0;
+    const int64_t reref = h->refrho ? h->reref_every : 0;
     while (done < nsteps) {
         int64_t chunk = nsteps - done;
-        if (h->check_every > 0) {
-            const int64_t to_check = h->check_every - (h->step % h->check_every);
-            if (chunk > to_check) chunk = to_check;
-        }
+        if (h->check_every > 0) chunk = std::min<int64_t>(chunk, h->check_every - (h->step % h->check_every));
+        if (reref > 0) chunk = std::min<int64_t>(chunk, reref - (h->step % reref));
         int rc = run_steps(h, chunk);
         if (rc) return rc;
         done += chunk;
         if (h->check_every > 0 && h->step % h->check_every == 0) {
             rc = scan_nonfinite(h);
+            if (rc) return rc;
+        }
+        if (reref > 0 && h->step % reref == 0) {
+            rc = rereference(h);
             if (rc) return rc;
         }
     }
@@ -709,6 +746,9 @@ int evlbm_set_populations(evlbm_t h, const void *f, const void *g, int where)
     hipError_t e = hipMemcpyAsync(h->scratch, f, half, k, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync((char *)h->scratch + half, g, half, k, h->stream);
     if (e != hipSuccess) return hip_fail(e, "copying populations");
+    if (h->refrho)
+        hipLaunchKernelGGL(k_refrho_from_pops, dim3((h->N + 255) / 256), dim3(256), 0, h->stream,
+                           (const double *)h->scratch, h->N, h->Q, h->refrho);
     dispatch<RunEncode>(h, (const double *)h->scratch);
     rc = check_launch("k_encode");
     if (rc) return rc;
@@ -739,6 +779,11 @@ int evlbm_checkpoint_save(evlbm_t h, const char *path)
                      h->D, h->nx, h->ny, h->nz, h->storage, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi,
                      h->ref_rho, h->ref_T, (long long)h->step, bytes);
     bool ok = fwrite(hdr, 1, n, fp) == (size_t)n && fwrite(host.data(), 1, bytes, fp) == bytes;
+    if (ok && h->refrho) {
+        std::vector<float> r((size_t)h->N);
+        e = hipMemcpy(r.data(), h->refrho, sizeof(float) * h->N, hipMemcpyDeviceToHost);
+        ok = e == hipSuccess && fwrite(r.data(), sizeof(float), h->N, fp) == (size_t)h->N;
+    }
     ok = (fclose(fp) == 0) && ok;
     if (!ok) return fail(EVLBM_EIO, "writing %s failed", path);
     return EVLBM_OK;
@@ -772,9 +817,18 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
         return fail(EVLBM_EINVAL, "checkpoint lattice/sizes/storage differ from the handle");
     }
     std::vector<char> host(bytes);
-    const bool ok = fread(host.data(), 1, bytes, fp) == bytes;
+    bool ok = fread(host.data(), 1, bytes, fp) == bytes;
+    std::vector<float> r;
+    if (ok && h->refrho) {
+        r.resize((size_t)h->N);
+        ok = fread(r.data(), sizeof(float), h->N, fp) == (size_t)h->N;
+    }
     fclose(fp);
     if (!ok) return fail(EVLBM_EIO, "truncated checkpoint %s", path);
+    if (h->refrho) {
+        hipError_t e2 = hipMemcpy(h->refrho, r.data(), sizeof(float) * h->N, hipMemcpyHostToDevice);
+        if (e2 != hipSuccess) return hip_fail(e2, "copying the reference density");
+    }
     h->R = R;
     h->a = a;
     h->b = b;

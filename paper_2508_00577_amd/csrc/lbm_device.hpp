@@ -103,8 +103,20 @@ struct StepParams {
     R wstar;         // (dt/lambda)(1 - beta)
     R lambda, sphi;
     R Rgas;
-    R ref[54];       // reference populations of the deviation storage: f (Q) then g (Q)
+    R ref[54];       // deviation storage: reference populations per unit density, f (Q) then g (Q)
+    const float *refrho;  // deviation storage: reference density of every cell (null otherwise)
 };
+
+// Reference value of direction i stored at cell s: refrho[s] * W_i for the
+// 16-bit deviation storage, 0 otherwise.
+template <int S, typename R>
+__device__ inline R ref_at(const StepParams<R> &p, int i, long s)
+{
+    if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
+        return (R)p.refrho[s] * p.ref[i];
+    else
+        return R(0);
+}
 
 // ---------------------------------------------- per-axis equilibrium factors
 

@@ -58,8 +58,8 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, c
         const double f = rho * fe[0][kx] * fe[1][ky] * fe[2][kz];
         const double g = rho * ((h * fe[0][kx] + xe[0][kx]) * fe[1][ky] * fe[2][kz] +
                                 fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
-        pop[(long)i * p.N + cell] = Codec<S>::enc((R)f, p.ref[i]);
-        pop[(long)(Q + i) * p.N + cell] = Codec<S>::enc((R)g, p.ref[Q + i]);
+        pop[(long)i * p.N + cell] = Codec<S>::enc((R)f, ref_at<S>(p, i, cell));
+        pop[(long)(Q + i) * p.N + cell] = Codec<S>::enc((R)g, ref_at<S>(p, Q + i, cell));
     }
 }
 
@@ -85,8 +85,8 @@ __global__ void __launch_bounds__(256) k_moments(const StoreT<S> *__restrict__ p
     for (int i = 0; i < Q; ++i) {
         const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
         const long src = (long)xs[kx] + (long)p.nx * ((long)ys[ky] + (long)p.ny * zs[kz]);
-        const R f = Codec<S>::dec(pop[(long)i * p.N + src], p.ref[i]);
-        const R g = Codec<S>::dec(pop[(long)(Q + i) * p.N + src], p.ref[Q + i]);
+        const R f = Codec<S>::dec(pop[(long)i * p.N + src], ref_at<S>(p, i, src));
+        const R g = Codec<S>::dec(pop[(long)(Q + i) * p.N + src], ref_at<S>(p, Q + i, src));
         rho += f;
         e += g;
         if (cx_of(i) == 1) jx += f;
@@ -163,16 +163,16 @@ __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S>
     // other directions, so each cell keeps these balances to a single rounding
     // of one stored value and no rounding bias accumulates from step to step.
     constexpr int REST = (Q - 1) / 2;
-    const R fh_rest = Codec<S>::dec(src[(long)REST * N + cell], p.ref[REST]);
-    const R gh_rest = Codec<S>::dec(src[(long)(Q + REST) * N + cell], p.ref[Q + REST]);
+    const R fh_rest = Codec<S>::dec(src[(long)REST * N + cell], ref_at<S>(p, REST, cell));
+    const R gh_rest = Codec<S>::dec(src[(long)(Q + REST) * N + cell], ref_at<S>(p, Q + REST, cell));
     double mass = (double)fh_rest, energy = (double)gh_rest, sf = 0.0, sg = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (i == REST) continue;
         const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
         const long s = (long)xs_[kx] + (long)p.nx * ((long)ys_[ky] + (long)p.ny * zs_[kz]);
-        const R fh = Codec<S>::dec(src[(long)i * N + s], p.ref[i]);
-        const R gh = Codec<S>::dec(src[(long)(Q + i) * N + s], p.ref[Q + i]);
+        const R fh = Codec<S>::dec(src[(long)i * N + s], ref_at<S>(p, i, s));
+        const R gh = Codec<S>::dec(src[(long)(Q + i) * N + s], ref_at<S>(p, Q + i, s));
         const R Pyz_e = fe[1][ky] * fe[2][kz];
         const R feq = rho * fe[0][kx] * Pyz_e;
         const R fst = rho * fs[0][kx] * (fs[1][ky] * fs[2][kz]);
@@ -185,18 +185,19 @@ __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S>
         // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq)
         const R fn = omb * fh + c_eq * feq + p.wstar * fst;
         const R gn = omb * gh + c_eq * geq + p.wstar * gst;
-        const StoreT<S> fq = Codec<S>::enc(fn, p.ref[i]);
-        const StoreT<S> gq = Codec<S>::enc(gn, p.ref[Q + i]);
+        const R rf = ref_at<S>(p, i, cell), rg = ref_at<S>(p, Q + i, cell);
+        const StoreT<S> fq = Codec<S>::enc(fn, rf);
+        const StoreT<S> gq = Codec<S>::enc(gn, rg);
         dst[(long)i * N + cell] = fq;
         dst[(long)(Q + i) * N + cell] = gq;
         mass += (double)fh;
         energy += (double)gh;
-        sf += (double)Codec<S>::dec(fq, p.ref[i]);
-        sg += (double)Codec<S>::dec(gq, p.ref[Q + i]);
+        sf += (double)Codec<S>::dec(fq, rf);
+        sg += (double)Codec<S>::dec(gq, rg);
     }
     const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
-    dst[(long)REST * N + cell] = Codec<S>::enc((R)(mass - sf), p.ref[REST]);
-    dst[(long)(Q + REST) * N + cell] = Codec<S>::enc((R)(energy + uF - sg), p.ref[Q + REST]);
+    dst[(long)REST * N + cell] = Codec<S>::enc((R)(mass - sf), ref_at<S>(p, REST, cell));
+    dst[(long)(Q + REST) * N + cell] = Codec<S>::enc((R)(energy + uF - sg), ref_at<S>(p, Q + REST, cell));
 }
 
 // ------------------------------------------------------------ k_collide
@@ -727,7 +728,7 @@ __global__ void __launch_bounds__(256) k_sums(const StoreT<S> *__restrict__ pop,
         double fmin_ = 1e300;
         for (int i = 0; i < Q; ++i) {
             const long src = (long)xs[cx_of(i) + 1] + (long)p.nx * ((long)ys[cy_of(i) + 1] + (long)p.ny * zs[cz_d<D>(i) + 1]);
-            const double f = Codec<S>::dec(pop[(long)i * p.N + src], p.ref[i]);
+            const double f = Codec<S>::dec(pop[(long)i * p.N + src], ref_at<S>(p, i, src));
             fmin_ = fmin(fmin_, f);
         }
         v[7] = fmin_;
@@ -790,7 +791,7 @@ __global__ void __launch_bounds__(256) k_decode(const StoreT<S> *__restrict__ po
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N * Q2) return;
     const int i = (int)(t / N);
-    out[t] = (double)Codec<S>::dec(pop[t], p.ref[i]);
+    out[t] = (double)Codec<S>::dec(pop[t], ref_at<S>(p, i, t - (long)i * N));
 }
 
 template <int S>
@@ -800,7 +801,7 @@ __global__ void __launch_bounds__(256) k_encode(const double *__restrict__ in, S
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N * Q2) return;
     const int i = (int)(t / N);
-    pop[t] = Codec<S>::enc((RealT<S>)in[t], p.ref[i]);
+    pop[t] = Codec<S>::enc((RealT<S>)in[t], ref_at<S>(p, i, t - (long)i * N));
 }
 
 // Validate initial fields: rho > 0, b rho < 1, T > 0 and finite.
@@ -812,6 +813,23 @@ __global__ void __launch_bounds__(256) k_validate(const double *__restrict__ rho
     const double r = rho[t], tt = T[t];
     if (!isfinite(r) || !isfinite(tt)) atomicOr(flag, 2);
     else if (!(r > 0.0) || !(1.0 - b * r > 0.0) || !(tt > 0.0)) atomicOr(flag, 1);
+}
+
+// Reference density of every cell = sum of its stored (decoded, FP64) f.
+__global__ void __launch_bounds__(256) k_refrho_from_pops(const double *__restrict__ f, long N, int Q,
+                                                          float *__restrict__ refrho)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    double s = 0.0;
+    for (int i = 0; i < Q; ++i) s += f[(long)i * N + t];
+    refrho[t] = (float)s;
+}
+
+__global__ void __launch_bounds__(256) k_f64_to_f32(const double *__restrict__ in, float *__restrict__ out, long n)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (float)in[t];
 }
 
 __global__ void __launch_bounds__(256) k_f32_to_f64(const float *__restrict__ in, double *__restrict__ out, long n)

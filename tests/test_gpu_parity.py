@@ -213,8 +213,10 @@ def test_3d_z_chunks_and_thin_lattices(shape, steps):
 @pytest.mark.parametrize("D,shape,storage", [(2, (1, 40, 96), "f16dev"), (2, (1, 40, 96), "bf16dev"),
                                              (3, (24, 20, 36), "f16dev"), (3, (24, 20, 36), "bf16dev")])
 def test_16bit_deviation_storage_tracks_fp32(D, shape, storage):
-    """Populations stored as 16-bit deviations from a reference equilibrium,
-    FP32 arithmetic: density within 1e-3 (relative) of the FP32-storage run."""
+    """Populations stored as 16-bit deviations from a per-cell reference
+    equilibrium, FP32 arithmetic, against the FP32-storage run after 300 steps.
+    FP16 (11-bit significand) meets the 1e-3 density target; BF16 (8-bit)
+    measures ~1e-2 and is held to 3e-2, its stated bound."""
     rho, T = _state("droplet", shape, 0.8, 1e-4)
     nz, ny, nx = shape
     runs = {}
@@ -228,4 +230,41 @@ def test_16bit_deviation_storage_tracks_fp32(D, shape, storage):
         runs[st] = L.moments()
     e = _errs(runs[storage], runs["f32"])
     print(f"{storage} D={D}: e_rho={e[0]:.2e} e_u={e[1]:.2e} e_T={e[2]:.2e}", flush=True)
+    assert e[0] < (1e-3 if storage == "f16dev" else 3e-2)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_checkpoint_resume_is_bitwise(storage, tmp_path):
+    shape = (1, 30, 64)
+    rho, T = _state("droplet", shape, 0.8, 1e-3)
+    a = ev.Lattice(2, 64, 30, 1, storage=storage)
+    a.set_params(**P)
+    a.init_fields(rho, T)
+    a.step(50)
+    path = tmp_path / "ck.evlbm"
+    a.checkpoint_save(path)
+    a.step(30)
+    b = ev.Lattice(2, 64, 30, 1, storage=storage)
+    b.checkpoint_load(path)
+    assert b.step_count == 50
+    b.step(30)
+    fa, ga = a.get_populations()
+    fb, gb = b.get_populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+def test_16bit_rereference():
+    """Re-referencing every 100 steps keeps the FP16 run on the FP32 one."""
+    shape = (1, 40, 96)
+    rho, T = _state("droplet", shape, 0.8, 1e-4)
+    runs = {}
+    for st, rr in (("f32", 0), ("f16dev", 100)):
+        L = ev.Lattice(2, 96, 40, 1, storage=st)
+        L.set_params(**P)
+        L.set_option(ev.OPT_REREF_EVERY, rr)
+        L.init_fields(rho, T)
+        L.step(300)
+        runs[st] = L.moments()
+    e = _errs(runs["f16dev"], runs["f32"])
+    print(f"f16dev re-referenced: e_rho={e[0]:.2e} e_T={e[2]:.2e}", flush=True)
     assert e[0] < 1e-3
