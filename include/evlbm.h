@@ -164,6 +164,53 @@ int evlbm_eos_coexistence(double R, double a, double b, double T, double out[3])
  * Errors: EINVAL, ENOMEM, EHIP. */
 int evlbm_copy_probe(double bytes, int reps, double *gbps_out);
 
+/* ------------------------------------------------------------------------
+ * Batched D2Q9 domains (a sweep over many uneven periodic domains sharing the
+ * EOS and relaxation parameters, e.g. a T/Tc sweep).  All domains advance
+ * together: each step is one persistent launch of the moment kernel and one
+ * of the stencil + collision kernel over the tiles of every domain, replayed
+ * from captured hipGraphs.  A domain of the batch evolves bit for bit as the
+ * same domain stepped alone as a lattice of the same storage.
+ * ------------------------------------------------------------------------ */
+typedef struct evlbm_batch *evlbm_batch_t;
+typedef struct {
+    int nx, ny;
+} evlbm_domain_desc;
+
+/* Create a batch of n domains (sizes d[k]) with the given storage on
+ * `stream` (a hipStream_t).  Errors: EINVAL, ENOMEM. */
+int evlbm_batch_create(int n, const evlbm_domain_desc *d, int storage, void *stream, evlbm_batch_t *out);
+int evlbm_batch_destroy(evlbm_batch_t b);
+
+/* Shared parameters (as evlbm_set_eos, evlbm_set_relaxation, EVLBM_OPT_SPHI)
+ * and the 16-bit storage reference state. */
+int evlbm_batch_set_params(evlbm_batch_t b, double R, double a, double bexcl, double kappa, double tau,
+                           double lambda, double sphi);
+int evlbm_batch_set_reference(evlbm_batch_t b, double ref_rho, double ref_T);
+
+/* Initialise domain k from host FP64 fields rho[N_k], u[2 N_k] (nullable), T[N_k].
+ * Errors: EINVAL, ENONPHYS, ENONFINITE. */
+int evlbm_batch_init_domain(evlbm_batch_t b, int k, const double *rho, const double *u, const double *T);
+
+/* Advance every domain nsteps.  Errors: ESTATE (a domain not initialised). */
+int evlbm_batch_step(evlbm_batch_t b, int64_t nsteps);
+
+/* Moments (rho, u[2 N_k], T) of domain k into host FP64 arrays; blocks. */
+int evlbm_batch_read(evlbm_batch_t b, int k, double *rho, double *u, double *T);
+
+/* Decoded populations f[9 N_k], g[9 N_k] of domain k (host FP64); blocks. */
+int evlbm_batch_get_populations(evlbm_batch_t b, int k, double *f, double *g);
+
+/* Tile shape of the persistent kernels: 0 = 64x4, 1 = 32x8, 2 = 128x2, 3 = 64x8. */
+int evlbm_batch_set_tile(evlbm_batch_t b, int variant);
+
+/* Time `steps` steps with each tile shape on the current state (restored
+ * afterwards), select the fastest; best and ms_per_step[4] (nullable) out. */
+int evlbm_batch_autotune(evlbm_batch_t b, int steps, int *best, double *ms_per_step);
+
+/* Total cells, tiles of the current shape, the shape index and its size. */
+int evlbm_batch_info(evlbm_batch_t b, int64_t *cells, int *ntiles, int *variant, int *tile_x, int *tile_y);
+
 /* Build information: "gfx950 <storage variants> <date>" (static string). */
 const char *evlbm_version(void);
 

@@ -70,6 +70,17 @@ def lib():
         L.evlbm_profile_step.argtypes = [_vp, ctypes.c_int, _dp]
         L.evlbm_eos_coexistence.argtypes = [ctypes.c_double] * 4 + [_dp]
         L.evlbm_copy_probe.argtypes = [ctypes.c_double, ctypes.c_int, _dp]
+        L.evlbm_batch_create.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+        L.evlbm_batch_destroy.argtypes = [_vp]
+        L.evlbm_batch_set_params.argtypes = [_vp] + [ctypes.c_double] * 7
+        L.evlbm_batch_set_reference.argtypes = [_vp, ctypes.c_double, ctypes.c_double]
+        L.evlbm_batch_init_domain.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
+        L.evlbm_batch_step.argtypes = [_vp, ctypes.c_int64]
+        L.evlbm_batch_read.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
+        L.evlbm_batch_get_populations.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+        L.evlbm_batch_set_tile.argtypes = [_vp, ctypes.c_int]
+        L.evlbm_batch_autotune.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp]
+        L.evlbm_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)] + [ctypes.POINTER(ctypes.c_int)] * 4
         _lib = L
     return _lib
 
@@ -242,3 +253,101 @@ class Lattice:
 
     def checkpoint_load(self, path):
         _check(lib().evlbm_checkpoint_load(self._h, str(path).encode()))
+
+
+TILE_SHAPES = [(64, 4), (32, 8), (128, 2), (64, 8)]
+
+
+class Batch:
+    """Many periodic D2Q9 domains of uneven sizes advanced together.
+
+    `sizes` is a list of (nx, ny).  Fields of domain k are [1, ny, nx] arrays.
+    """
+
+    def __init__(self, sizes, storage="f32", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a visible GPU")
+        self.sizes = [(int(a), int(b)) for a, b in sizes]
+        self.n = len(self.sizes)
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        desc = (ctypes.c_int * (2 * self.n))(*[v for s in self.sizes for v in s])
+        h = _vp()
+        _check(lib().evlbm_batch_create(self.n, ctypes.cast(desc, _vp), self.storage, _vp(self.stream.cuda_stream),
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.evlbm_batch_destroy(h)
+            self._h = None
+
+    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0):
+        _check(lib().evlbm_batch_set_params(self._h, R, a, b, kappa, tau, lam, sphi))
+
+    def set_reference(self, rho_ref, T_ref):
+        _check(lib().evlbm_batch_set_reference(self._h, float(rho_ref), float(T_ref)))
+
+    def init_domain(self, k, rho, T, u=None):
+        nx, ny = self.sizes[k]
+        rho, T = _host(rho), _host(T)
+        assert rho.size == nx * ny and T.size == nx * ny
+        u = None if u is None else _host(u)
+        _check(lib().evlbm_batch_init_domain(self._h, int(k), _ptr(rho), _ptr(u), _ptr(T)))
+
+    def step(self, n=1):
+        _check(lib().evlbm_batch_step(self._h, int(n)))
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def moments(self, k):
+        nx, ny = self.sizes[k]
+        rho, T = np.zeros((1, ny, nx)), np.zeros((1, ny, nx))
+        u = np.zeros((2, 1, ny, nx))
+        _check(lib().evlbm_batch_read(self._h, int(k), _ptr(rho), _ptr(u), _ptr(T)))
+        return rho, u, T
+
+    def get_populations(self, k):
+        nx, ny = self.sizes[k]
+        f, g = np.zeros((9, 1, ny, nx)), np.zeros((9, 1, ny, nx))
+        _check(lib().evlbm_batch_get_populations(self._h, int(k), _ptr(f), _ptr(g)))
+        return f, g
+
+    def set_tile(self, variant):
+        _check(lib().evlbm_batch_set_tile(self._h, int(variant)))
+
+    def info(self):
+        cells = ctypes.c_int64()
+        nt, v, tx, ty = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().evlbm_batch_info(self._h, ctypes.byref(cells), ctypes.byref(nt), ctypes.byref(v),
+                                      ctypes.byref(tx), ctypes.byref(ty)))
+        return dict(cells=cells.value, tiles=nt.value, variant=v.value, tile=(tx.value, ty.value))
+
+    def autotune(self, steps=20, cache=None):
+        """Pick the fastest tile shape (timed on this batch); with `cache`, a JSON
+        file keyed by the domain sizes and storage, reuse a previous choice."""
+        import hashlib
+        import json
+        key = hashlib.sha256(json.dumps([self.storage, self.sizes]).encode()).hexdigest()[:16]
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+            if key in table:
+                self.set_tile(table[key]["variant"])
+                return table[key]
+        best = ctypes.c_int()
+        ms = np.zeros(4)
+        _check(lib().evlbm_batch_autotune(self._h, int(steps), ctypes.byref(best), ms.ctypes.data_as(_dp)))
+        entry = {"variant": int(best.value), "tile": TILE_SHAPES[best.value], "ms_per_step": ms.tolist()}
+        if cache:
+            table = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    table = json.load(fh)
+            table[key] = entry
+            with open(cache, "w") as fh:
+                json.dump(table, fh, indent=1)
+        return entry

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "evlbm_internal.hpp"
+#include "evlbm_params.hpp"
 #include "lbm_kernels.hpp"
 
 using namespace evlbm;
@@ -70,30 +71,12 @@ void reference_populations(int D, double R, double b, double rho, double T, doub
 template <typename R>
 StepParams<R> make_params(const evlbm_lattice *h)
 {
-    StepParams<R> p;
+    StepParams<R> p = model_params<R>(h->D, h->storage, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi,
+                                      h->ref_rho, h->ref_T);
     p.nx = h->nx;
     p.ny = h->ny;
     p.nz = h->nz;
     p.N = h->N;
-    p.a = (R)h->a;
-    p.b = (R)h->b;
-    p.kappa = (R)h->kappa;
-    const double beta = 1.0 / (2.0 * h->tau + 1.0);
-    p.two_beta = (R)(2.0 * beta);
-    p.wstar = (R)((1.0 / h->lambda) * (1.0 - beta));
-    p.lambda = (R)h->lambda;
-    p.sphi = (R)h->sphi;
-    p.Rgas = (R)h->R;
-    double ref[54];
-    if (h->storage == EVLBM_F16DEV || h->storage == EVLBM_BF16DEV) {
-        // per unit density: the equilibrium at rest is proportional to rho
-        // at fixed theta and RT
-        reference_populations(h->D, h->R, h->b, h->ref_rho, h->ref_T, ref);
-        for (int i = 0; i < 54; ++i) ref[i] /= h->ref_rho;
-    } else {
-        for (int i = 0; i < 54; ++i) ref[i] = 0.0;
-    }
-    for (int i = 0; i < 54; ++i) p.ref[i] = (R)ref[i];
     p.refrho = h->refrho;
     return p;
 }

@@ -68,14 +68,11 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, c
 // m[0] = rho, m[1..D] = j, m[D+1] = e of the pulled populations
 // fh_i(x) = f_i(x - c_i).  Grid (ceil(nx/bx), ny, nz), block (bx).
 template <int D, int S>
-__global__ void __launch_bounds__(256) k_moments(const StoreT<S> *__restrict__ pop, RealT<S> *__restrict__ m,
-                                                 StepParams<RealT<S>> p)
+__device__ inline void moments_at(const StoreT<S> *__restrict__ pop, RealT<S> *__restrict__ m,
+                                  const StepParams<RealT<S>> &p, int x, int y, int z)
 {
     using R = RealT<S>;
     constexpr int Q = Lat<D>::Q;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= p.nx) return;
-    const int y = blockIdx.y, z = blockIdx.z;
     // source coordinate x - c for c = -1, 0, +1
     const int xs[3] = {x + 1 == p.nx ? 0 : x + 1, x, x == 0 ? p.nx - 1 : x - 1};
     const int ys[3] = {y + 1 == p.ny ? 0 : y + 1, y, y == 0 ? p.ny - 1 : y - 1};
@@ -102,6 +99,15 @@ __global__ void __launch_bounds__(256) k_moments(const StoreT<S> *__restrict__ p
     m[2 * p.N + cell] = jy;
     if (D == 3) m[3 * p.N + cell] = jz;
     m[(D + 1) * p.N + cell] = e;
+}
+
+template <int D, int S>
+__global__ void __launch_bounds__(256) k_moments(const StoreT<S> *__restrict__ pop, RealT<S> *__restrict__ m,
+                                                 StepParams<RealT<S>> p)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= p.nx) return;
+    moments_at<D, S>(pop, m, p, x, blockIdx.y, blockIdx.z);
 }
 
 // Equilibria (eq. feq, f_star, geq, gstar with eq. g_corr), shifted state
@@ -215,10 +221,12 @@ struct TileShape {
     static constexpr int NT = BX * BY * BZ;
 };
 
+// One BX x BY x BZ tile of cells with origin (x0, y0, z0); the block's
+// threads are (threadIdx.x, threadIdx.y, threadIdx.z).
 template <int D, int S, int BX, int BY, int BZ>
-__global__ void __launch_bounds__(BX *BY *BZ)
-    k_collide(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
-              StepParams<RealT<S>> p)
+__device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
+                                     const RealT<S> *__restrict__ m, const StepParams<RealT<S>> &p, int x0, int y0,
+                                     int z0)
 {
     using R = RealT<S>;
     using TS = TileShape<D, BX, BY, BZ>;
@@ -230,7 +238,6 @@ __global__ void __launch_bounds__(BX *BY *BZ)
     __shared__ R s_f1[TS::NF * TS::N1];
 
     const int tid = threadIdx.x + BX * (threadIdx.y + BY * threadIdx.z);
-    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * BY, z0 = blockIdx.z * BZ;
     const long N = p.N;
 
     // rho on the tile + 3 halo (periodic)
@@ -325,6 +332,14 @@ __global__ void __launch_bounds__(BX *BY *BZ)
         qp[2] = p.lambda * (P0 * lds_grad<D, 2, R>(s_f1 + F_TD * TS::N1, c1, SY, SZ) + u[2] * Phip);
     }
     collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, one_m_br, theta, u, F, Phi, qp);
+}
+
+template <int D, int S, int BX, int BY, int BZ>
+__global__ void __launch_bounds__(BX *BY *BZ)
+    k_collide(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
+              StepParams<RealT<S>> p)
+{
+    collide_block<D, S, BX, BY, BZ>(src, dst, m, p, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * BZ);
 }
 
 // ------------------------------------------------------- k_collide_zm (3D)
@@ -805,7 +820,7 @@ __global__ void __launch_bounds__(256) k_encode(const double *__restrict__ in, S
 }
 
 // Validate initial fields: rho > 0, b rho < 1, T > 0 and finite.
-__global__ void __launch_bounds__(256) k_validate(const double *__restrict__ rho, const double *__restrict__ T, long N,
+static __global__ void __launch_bounds__(256) k_validate(const double *__restrict__ rho, const double *__restrict__ T, long N,
                                                   double b, int *__restrict__ flag)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -816,7 +831,7 @@ __global__ void __launch_bounds__(256) k_validate(const double *__restrict__ rho
 }
 
 // Reference density of every cell = sum of its stored (decoded, FP64) f.
-__global__ void __launch_bounds__(256) k_refrho_from_pops(const double *__restrict__ f, long N, int Q,
+static __global__ void __launch_bounds__(256) k_refrho_from_pops(const double *__restrict__ f, long N, int Q,
                                                           float *__restrict__ refrho)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -826,13 +841,13 @@ __global__ void __launch_bounds__(256) k_refrho_from_pops(const double *__restri
     refrho[t] = (float)s;
 }
 
-__global__ void __launch_bounds__(256) k_f64_to_f32(const double *__restrict__ in, float *__restrict__ out, long n)
+static __global__ void __launch_bounds__(256) k_f64_to_f32(const double *__restrict__ in, float *__restrict__ out, long n)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) out[t] = (float)in[t];
 }
 
-__global__ void __launch_bounds__(256) k_f32_to_f64(const float *__restrict__ in, double *__restrict__ out, long n)
+static __global__ void __launch_bounds__(256) k_f32_to_f64(const float *__restrict__ in, double *__restrict__ out, long n)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) out[t] = (double)in[t];
