@@ -211,6 +211,47 @@ int evlbm_batch_autotune(evlbm_batch_t b, int steps, int *best, double *ms_per_s
 /* Total cells, tiles of the current shape, the shape index and its size. */
 int evlbm_batch_info(evlbm_batch_t b, int64_t *cells, int *ntiles, int *variant, int *tile_x, int *tile_y);
 
+/* ------------------------------------------------------------------------
+ * Warm-start network: (T/Tc, R, r/R) -> 3 x 64 tanh hidden layers -> rho/rho_c,
+ * FP32 parameters in the flat layout W1[64][3], b1[64], W2[64][64], b2[64],
+ * W3[64][64], b3[64], W4[64], b4 (8641 values); inputs normalised as
+ * x1 = (T/Tc - 0.8)/0.15, x2 = (R - 47.5)/32.5, x3 = r/R - 1.  Trained on
+ * the GPU (mean squared error, Adam with beta1 0.9, beta2 0.999, eps 1e-8) on
+ * droplet profiles the solver itself produces; used to seed new droplets.
+ * Host arrays: X[n][3], Y[n].
+ * ------------------------------------------------------------------------ */
+typedef struct evlbm_mlp *evlbm_mlp_t;
+
+enum { EVLBM_PROFILE_TANH = 0, EVLBM_PROFILE_MLP = 1 };
+
+int evlbm_mlp_create(void *stream, evlbm_mlp_t *out);
+int evlbm_mlp_destroy(evlbm_mlp_t m);
+int evlbm_mlp_num_params(void);
+/* Set or read the parameters (n must be 8641); set resets the Adam state. */
+int evlbm_mlp_set_params(evlbm_mlp_t m, const float *params, int n);
+int evlbm_mlp_get_params(evlbm_mlp_t m, float *params, int n);
+/* Outputs Y[n] for inputs X[n][3]; blocks. */
+int evlbm_mlp_forward(evlbm_mlp_t m, const float *X, float *Y, int n);
+/* Gradient of the mean squared error (grad[8641], nullable) and the loss
+ * (nullable) at the current parameters; blocks. */
+int evlbm_mlp_grad(evlbm_mlp_t m, const float *X, const float *Y, int n, float *grad, float *loss);
+/* iters full-batch Adam steps with learning rate lr; loss_hist[iters]
+ * (nullable) receives the loss before each step; blocks. */
+int evlbm_mlp_train(evlbm_mlp_t m, const float *X, const float *Y, int n, int iters, float lr, float *loss_hist);
+/* Device FP64 density field rho_c * y(T/Tc, R, |x - c|/R) of a lattice of
+ * nx*ny*nz cells (nz = 1: 2D distance), enqueued on the network's stream. */
+int evlbm_mlp_density_field(evlbm_mlp_t m, int nx, int ny, int nz, double cx, double cy, double cz, double R,
+                            double Tr, double rho_c, double *rho_dev);
+
+/* Initialise a droplet of radius R centred at (cx, cy, cz) at T/Tc = Tr, at
+ * rest: TANH = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh((r - R)/width) with
+ * the coexistence densities; MLP = the network's profile, falling back to
+ * TANH when Tr or R lie outside [0.65, 0.97] x [12, 90] or the radial profile
+ * is non-finite, increasing in r or outside [0.5 rho_v, 1.2 rho_l].
+ * *used_mlp (nullable) tells which was used.  Needs a > 0, b > 0. */
+int evlbm_init_droplet(evlbm_t h, double cx, double cy, double cz, double R, double Tr, int profile, evlbm_mlp_t mlp,
+                       double width, int *used_mlp);
+
 /* Build information: "gfx950 <storage variants> <date>" (static string). */
 const char *evlbm_version(void);
 

@@ -80,6 +80,16 @@ def lib():
         L.evlbm_batch_get_populations.argtypes = [_vp, ctypes.c_int, _vp, _vp]
         L.evlbm_batch_set_tile.argtypes = [_vp, ctypes.c_int]
         L.evlbm_batch_autotune.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp]
+        _fp = ctypes.POINTER(ctypes.c_float)
+        L.evlbm_mlp_create.argtypes = [_vp, ctypes.POINTER(_vp)]
+        L.evlbm_mlp_destroy.argtypes = [_vp]
+        L.evlbm_mlp_set_params.argtypes = [_vp, _fp, ctypes.c_int]
+        L.evlbm_mlp_get_params.argtypes = [_vp, _fp, ctypes.c_int]
+        L.evlbm_mlp_forward.argtypes = [_vp, _fp, _fp, ctypes.c_int]
+        L.evlbm_mlp_grad.argtypes = [_vp, _fp, _fp, ctypes.c_int, _fp, _fp]
+        L.evlbm_mlp_train.argtypes = [_vp, _fp, _fp, ctypes.c_int, ctypes.c_int, ctypes.c_float, _fp]
+        L.evlbm_init_droplet.argtypes = [_vp] + [ctypes.c_double] * 5 + [ctypes.c_int, _vp, ctypes.c_double,
+                                                                         ctypes.POINTER(ctypes.c_int)]
         L.evlbm_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)] + [ctypes.POINTER(ctypes.c_int)] * 4
         _lib = L
     return _lib
@@ -248,6 +258,19 @@ class Lattice:
         assert f.size == self.Q * self.N and g.size == self.Q * self.N
         _check(lib().evlbm_set_populations(self._h, _ptr(f), _ptr(g), HOST_F64))
 
+    def init_droplet(self, radius, Tr, profile="tanh", mlp=None, centre=None, width=2.0):
+        """Droplet at rest at T/Tc = Tr: tanh profile between the coexistence
+        densities, or the network's profile (with the tanh fallback).  Returns
+        True when the network's profile was used."""
+        if centre is None:
+            centre = ((self.nx - 1) / 2.0, (self.ny - 1) / 2.0, (self.nz - 1) / 2.0)
+        used = ctypes.c_int()
+        prof = 1 if profile == "mlp" else 0
+        _check(lib().evlbm_init_droplet(self._h, float(centre[0]), float(centre[1]), float(centre[2]), float(radius),
+                                        float(Tr), prof, None if mlp is None else mlp._h, float(width),
+                                        ctypes.byref(used)))
+        return bool(used.value)
+
     def checkpoint_save(self, path):
         _check(lib().evlbm_checkpoint_save(self._h, str(path).encode()))
 
@@ -351,3 +374,63 @@ class Batch:
             with open(cache, "w") as fh:
                 json.dump(table, fh, indent=1)
         return entry
+
+
+NPARAM = 8641
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class MLP:
+    """The warm-start network on the GPU (forward, gradient, Adam training)."""
+
+    def __init__(self, params=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a visible GPU")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        h = _vp()
+        _check(lib().evlbm_mlp_create(_vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        if params is not None:
+            self.set_params(params)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.evlbm_mlp_destroy(h)
+            self._h = None
+
+    def set_params(self, params):
+        p = _f32(params)
+        _check(lib().evlbm_mlp_set_params(self._h, _fptr(p), p.size))
+
+    def params(self):
+        p = np.zeros(NPARAM, dtype=np.float32)
+        _check(lib().evlbm_mlp_get_params(self._h, _fptr(p), NPARAM))
+        return p
+
+    def forward(self, X):
+        X = _f32(X).reshape(-1, 3)
+        Y = np.zeros(X.shape[0], dtype=np.float32)
+        _check(lib().evlbm_mlp_forward(self._h, _fptr(X), _fptr(Y), X.shape[0]))
+        return Y
+
+    def grad(self, X, Y):
+        X, Y = _f32(X).reshape(-1, 3), _f32(Y)
+        g = np.zeros(NPARAM, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        _check(lib().evlbm_mlp_grad(self._h, _fptr(X), _fptr(Y), X.shape[0], _fptr(g), _fptr(loss)))
+        return g, float(loss[0])
+
+    def train(self, X, Y, iters, lr=1e-3):
+        X, Y = _f32(X).reshape(-1, 3), _f32(Y)
+        hist = np.zeros(int(iters), dtype=np.float32)
+        _check(lib().evlbm_mlp_train(self._h, _fptr(X), _fptr(Y), X.shape[0], int(iters), float(lr), _fptr(hist)))
+        return hist

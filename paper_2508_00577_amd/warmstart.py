@@ -1,0 +1,177 @@
+"""Learned warm start for droplet runs.
+
+The solver produces long-run droplet profiles; their radial means become
+training samples (T/Tc, R, r/R) -> rho/rho_c for the network, which is
+trained on the GPU by the library's own kernels and then seeds new droplets
+through evlbm_init_droplet (with the tanh profile as fallback).  The study
+compares the number of steps to equilibrium of network-seeded and
+tanh-seeded runs and the final density difference between them.
+
+Steps to equilibrium: the plain (tanh-seeded) run is advanced for a long
+horizon and its final density field is the reference; a run has reached
+equilibrium at the first check (every `check` steps) where its density is
+within `tol` (max relative difference) of that reference.  The same reference
+judges the final error of the network-seeded run.  (The thermal relaxation of
+latent heat across the domain is slow, so a drift-rate criterion is not met
+within practical horizons by either run.)
+
+A periodic box conserves mass and total energy, so two runs can only end in
+the same state if they start with the same mass and energy.  The sharp tanh
+profile carries excess interface energy that turns into heat; the matched
+warm start therefore scales the network's density field to the plain run's
+mass and sets its uniform temperature so that the total energy
+sum[rho E - a rho^2 + (kappa/2)|grad rho|^2] (global sums of the library)
+equals the plain run's.  The unmatched warm start keeps T = Tr Tc.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import MLP, Lattice
+
+
+def radial_profile(rho, centre, R, dr=0.5, rmax_factor=3.0):
+    """Mean density on radial bins of width dr up to rmax_factor * R around
+    centre (2D when rho has one z-plane).  Returns (r_mid, mean) of non-empty bins."""
+    nz, ny, nx = rho.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2
+    if nz > 1:
+        r2 = r2 + (z - centre[2]) ** 2
+    r = np.sqrt(r2).ravel()
+    rmax = min(rmax_factor * R, 0.5 * min(s for s in rho.shape if s > 1) - 1.0)
+    nb = int(rmax / dr)
+    idx = np.floor(r / dr).astype(int)
+    keep = idx < nb
+    sums = np.bincount(idx[keep], weights=rho.ravel()[keep], minlength=nb)
+    cnt = np.bincount(idx[keep], minlength=nb)
+    ok = cnt > 0
+    mids = (np.arange(nb) + 0.5) * dr
+    return mids[ok], sums[ok] / cnt[ok]
+
+
+def run_to_equilibrium(L, max_steps, check=100, tol=1e-7, rho_c=1.0):
+    """Step until the equilibrium criterion holds; returns (steps, converged)."""
+    prev, _, _ = L.moments()
+    umax_prev = np.inf
+    steps = 0
+    while steps < max_steps:
+        L.step(check)
+        steps += check
+        rho, u, _ = L.moments()
+        drift = np.abs(rho - prev).max() / check
+        umax = np.abs(u).max()
+        if drift < tol * rho_c and umax >= umax_prev * (1 - 1e-3):
+            return steps, True
+        prev, umax_prev = rho, umax
+    return steps, False
+
+
+def droplet_run(shape, R, Tr, params, steps=None, profile="tanh", mlp=None, storage="f32", max_steps=40000,
+                check=100, tol=1e-7):
+    nz, ny, nx = shape
+    L = Lattice(3 if nz > 1 else 2, nx, ny, nz, storage=storage)
+    L.set_params(**params)
+    used = L.init_droplet(R, Tr, profile=profile, mlp=mlp)
+    if steps is not None:
+        L.step(steps)
+        return L, used, steps, None
+    n, conv = run_to_equilibrium(L, max_steps, check, tol, rho_c=1.0 / (3.0 * params["b"]))
+    return L, used, n, conv
+
+
+def training_samples(cases, shape, params, steps, rho_c):
+    """(X, Y) from the radial profiles of solver runs: cases = [(R, Tr), ...]."""
+    X, Y = [], []
+    nz, ny, nx = shape
+    centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
+    for R, Tr in cases:
+        L, _, _, _ = droplet_run(shape, R, Tr, params, steps=steps)
+        rho, _, _ = L.moments()
+        r, prof = radial_profile(rho, centre, R)
+        X.append(np.stack([np.full(r.size, Tr), np.full(r.size, R), r / R], 1))
+        Y.append(prof / rho_c)
+    return np.concatenate(X), np.concatenate(Y)
+
+
+def train_network(X, Y, init_params, iters, lr=1e-3):
+    net = MLP(init_params)
+    hist = net.train(X, Y, iters, lr)
+    return net, hist
+
+
+def network_density(net, shape, R, Tr, rho_c):
+    """rho_c y(Tr, R, |x - c|/R) on every cell, from the network (host FP64)."""
+    nz, ny, nx = shape
+    centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2
+    if nz > 1:
+        r2 = r2 + (z - centre[2]) ** 2
+    rr = (np.sqrt(r2) / R).ravel()
+    X = np.stack([np.full(rr.size, Tr), np.full(rr.size, R), rr], 1)
+    return (rho_c * net.forward(X).astype(np.float64)).reshape(shape)
+
+
+def seed_matched(L, net, R, Tr, params, target):
+    """Seed L from the network with the mass and total energy `target` (global
+    sums of a plain-seeded lattice).  Returns the temperature used."""
+    Tc = 8.0 * params["a"] / (27.0 * params["b"] * params["R"])
+    rho = network_density(net, L.shape, R, Tr, 1.0 / (3.0 * params["b"]))
+    rho *= target[0] / rho.sum()
+    T0 = Tr * Tc
+    L.init_fields(rho, np.full(L.shape, T0))
+    s = L.global_sums()
+    T1 = T0 + (target[5] - s[5]) / (1.5 * params["R"] * target[0])
+    L.init_fields(rho, np.full(L.shape, T1))
+    return T1
+
+
+def _first_within(snaps, ref, tol):
+    scale = np.abs(ref).max()
+    for n, rho in snaps:
+        if np.abs(rho - ref).max() < tol * scale:
+            return n
+    return None
+
+
+def warm_start_study(net, cases, shape, params, horizon=40000, check=500, tol=2e-2):
+    """For each (R, Tr), three seedings of the same droplet: the tanh profile
+    ("tanh"), the network profile at T = Tr Tc ("mlp") and the network profile
+    with the tanh run's mass and energy ("mlp_matched").  The tanh run's state
+    after `horizon` steps is the reference.  Reported per seeding: the initial
+    distance to it (max relative density difference), the first checked step
+    within `tol` of it (None if never) and the distance at the horizon; and
+    whether the network profile passed the fallback checks."""
+    out = []
+    nz, ny, nx = shape
+    for R, Tr in cases:
+        runs = {}
+        target = None
+        used = False
+        for prof in ("tanh", "mlp", "mlp_matched"):
+            L = Lattice(3 if nz > 1 else 2, nx, ny, nz, storage="f32")
+            L.set_params(**params)
+            if prof == "mlp_matched":
+                seed_matched(L, net, R, Tr, params, target)
+            else:
+                u = L.init_droplet(R, Tr, profile="mlp" if prof == "mlp" else "tanh",
+                                   mlp=net if prof == "mlp" else None)
+                used = used or (prof == "mlp" and u)
+            if prof == "tanh":
+                target = L.global_sums()
+            snaps = [(0, L.moments()[0].astype(np.float32))]
+            for n in range(check, horizon + 1, check):
+                L.step(check)
+                snaps.append((n, L.moments()[0].astype(np.float32)))
+            runs[prof] = snaps
+        ref = runs["tanh"][-1][1].astype(np.float64)
+        scale = np.abs(ref).max()
+        rec = dict(R=R, Tr=Tr, horizon=horizon, tol=tol, mlp_used=bool(used))
+        for prof, snaps in runs.items():
+            d = [(n, float(np.abs(r.astype(np.float64) - ref).max() / scale)) for n, r in snaps]
+            rec["err0_" + prof] = d[0][1]
+            rec["steps_" + prof] = next((n for n, e in d if e < tol), None)
+            rec["err_end_" + prof] = d[-1][1]
+        out.append(rec)
+    return out
