@@ -269,13 +269,10 @@ static int finish_reduce(evlbm_lattice *h, long nb, int nv, const int ops[8], do
     double *res = partial + nb * nv;
     int4 lo = make_int4(ops[0], ops[1], ops[2], ops[3]);
     int4 hi = make_int4(ops[4], ops[5], ops[6], ops[7]);
-    if (nv == 8)
-        hipLaunchKernelGGL((k_reduce_final<8>), dim3(8), dim3(64), 0, h->stream, partial, nb, lo, hi, res);
-    else
-        hipLaunchKernelGGL((k_reduce_final<9>), dim3(8), dim3(64), 0, h->stream, partial, nb, lo, hi, res);
+    hipLaunchKernelGGL(k_reduce_final, dim3(nv), dim3(256), 0, h->stream, partial, nb, lo, hi, res);
     int rc = check_launch("reduce");
     if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(out, res, sizeof(double) * 8, hipMemcpyDeviceToHost, h->stream);
+    hipError_t e = hipMemcpyAsync(out, res, sizeof(double) * nv, hipMemcpyDeviceToHost, h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -672,16 +669,11 @@ int evlbm_measure(evlbm_t h, int kind, const double *geom, double out[8])
     dispatch<RunMeasure>(h, kind, (const double *)g, (double *)h->scratch, nb);
     rc = check_launch("k_measure");
     if (rc) return rc;
-    // nine sums; the final reduction runs 8 lanes, so reduce the ninth on the host
     const int ops[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    double s[8];
+    double s[9];
     rc = finish_reduce(h, nb, 9, ops, s);
     if (rc) return rc;
-    std::vector<double> part((size_t)nb * 9);
-    hipError_t e = hipMemcpy(part.data(), h->scratch, sizeof(double) * nb * 9, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
-    double total = 0.0;
-    for (long b = 0; b < nb; ++b) total += part[b * 9 + 8];
+    const double total = s[8];
     const double n_in = s[3], n_out = s[7];
     const double rin = n_in > 0 ? s[0] / n_in : NAN, rout = n_out > 0 ? s[4] / n_out : NAN;
     out[0] = rin;

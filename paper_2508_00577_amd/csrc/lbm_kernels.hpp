@@ -664,8 +664,11 @@ __global__ void __launch_bounds__(256) k_readout(const R *__restrict__ m, const 
 
 // ------------------------------------------------------- FP64 reductions
 
-// Block-level FP64 sum of NV values, deterministic (fixed tree), then one
-// partial per block.  Op: 0 = sum, 1 = max, 2 = min.
+// Block-level FP64 reduction of NV values in a fixed tree, one partial per
+// block stored value-major: partial[k * gridDim.x + blockIdx.x].
+// Op: 0 = sum, 1 = max, 2 = min.
+__device__ inline double red_op(int op, double x, double y) { return op == 0 ? x + y : op == 1 ? fmax(x, y) : fmin(x, y); }
+
 template <int NV>
 __device__ inline void block_reduce_store(double v[NV], const int ops[NV], double *__restrict__ partial)
 {
@@ -675,40 +678,36 @@ __device__ inline void block_reduce_store(double v[NV], const int ops[NV], doubl
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double x = v[k];
-        for (int off = 32; off > 0; off >>= 1) {
-            double o = __shfl_xor(x, off, 64);
-            x = ops[k] == 0 ? x + o : ops[k] == 1 ? fmax(x, o) : fmin(x, o);
-        }
+        for (int off = 32; off > 0; off >>= 1) x = red_op(ops[k], x, __shfl_xor(x, off, 64));
         if (lane == 0) s_red[k][wid] = x;
     }
     __syncthreads();
     if (threadIdx.x < NV) {
         const int k = threadIdx.x;
         double x = s_red[k][0];
-        for (int w = 1; w < nw; ++w) x = ops[k] == 0 ? x + s_red[k][w] : ops[k] == 1 ? fmax(x, s_red[k][w]) : fmin(x, s_red[k][w]);
-        partial[(long)blockIdx.x * NV + k] = x;
+        for (int w = 1; w < nw; ++w) x = red_op(ops[k], x, s_red[k][w]);
+        partial[(long)k * gridDim.x + blockIdx.x] = x;
     }
 }
 
-template <int NV>
-__global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__ partial, long nblocks, const int4 ops_lo,
+// Final pass: block k reduces the nblocks partials of value k (coalesced,
+// 256 threads, fixed order) into out[k].
+static __global__ void __launch_bounds__(256) k_reduce_final(const double *__restrict__ partial, long nblocks, const int4 ops_lo,
                                                       const int4 ops_hi, double *__restrict__ out)
 {
-    // one block of 64 threads per value: lane-strided partial sums then a
-    // fixed-order wave reduction (deterministic).
+    __shared__ double s[256];
     const int k = blockIdx.x;
     const int ops[8] = {ops_lo.x, ops_lo.y, ops_lo.z, ops_lo.w, ops_hi.x, ops_hi.y, ops_hi.z, ops_hi.w};
-    const int op = ops[k];
+    const int op = ops[k < 8 ? k : 0];
     double x = op == 0 ? 0.0 : op == 1 ? -1e300 : 1e300;
-    for (long b = threadIdx.x; b < nblocks; b += 64) {
-        const double v = partial[b * NV + k];
-        x = op == 0 ? x + v : op == 1 ? fmax(x, v) : fmin(x, v);
+    for (long b = threadIdx.x; b < nblocks; b += 256) x = red_op(op, x, partial[(long)k * nblocks + b]);
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] = red_op(op, s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        double o = __shfl_xor(x, off, 64);
-        x = op == 0 ? x + o : op == 1 ? fmax(x, o) : fmin(x, o);
-    }
-    if (threadIdx.x == 0) out[k] = x;
+    if (threadIdx.x == 0) out[k] = s[0];
 }
 
 // Global sums of the readout state (FP64 accumulation), one cell per thread
