@@ -29,7 +29,7 @@ PROFILES = os.path.join(ROOT, "profiles")
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for name in ("lbm_kernels.hpp", "lbm_device.hpp"):
+    for name in ("lbm_kernels.hpp", "lbm_device.hpp", "evlbm_lattice.hip"):
         with open(os.path.join(ROOT, "paper_2508_00577_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

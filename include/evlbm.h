@@ -75,7 +75,9 @@ const char *evlbm_last_error(void);
  * given storage, bound to `stream` (a hipStream_t; NULL = default stream) on
  * the current device.  Allocates two population buffers (2*2Q*N values) and a
  * moment field.  Parameters start at R = 1, a = b = kappa = 0, tau = lambda = 1.
- * Errors: EINVAL (unknown lattice or storage, sizes <= 0, nz != 1 for D2Q9),
+ * Errors: EINVAL (unknown lattice or storage, sizes <= 0, nz != 1 for D2Q9,
+ * nx*ny*nz*8 >= 2^32 for FP64 storage or nx*ny*nz*4 >= 2^32 otherwise: the
+ * kernels address each per-direction array with 32-bit byte offsets),
  * ENOMEM, EHIP. */
 int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream, evlbm_t *out);
 

@@ -105,16 +105,18 @@ struct Ops {
                            make_params<R>(h));
     }
     // z-marching tile of the D3Q27 kernel: TX x TY columns, ZC planes per chunk
-    static constexpr int TX = (S == EVLBM_F64) ? 16 : 32;
-    static constexpr int TY = 8;
+    // (64 x 4 in FP32 and 16-bit storage: a row of the tile spans two 128-byte
+    // lines, so the pulled rows of the 18 directions with cx != 0 touch three)
+    static constexpr int TX = (S == EVLBM_F64) ? 16 : 64;
+    static constexpr int TY = (S == EVLBM_F64) ? 8 : 4;
     static constexpr int ZC = 32;
 
     static void collide(evlbm_lattice *h, const void *src, void *dst)
     {
         if (D == 3) {
-            dim3 grid((h->nx + TX - 1) / TX, (h->ny + TY - 1) / TY, (h->nz + ZC - 1) / ZC);
-            hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC>), grid, dim3(TX, TY), 0, h->stream, (const T *)src,
-                               (T *)dst, (const R *)h->m, make_params<R>(h));
+            const int nbx = (h->nx + TX - 1) / TX, nby = (h->ny + TY - 1) / TY, nbz = (h->nz + ZC - 1) / ZC;
+            hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC>), dim3(nbx * nby * nbz), dim3(TX, TY), 0, h->stream,
+                               (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby);
         } else {
             dim3 grid((h->nx + BX - 1) / BX, (h->ny + BY - 1) / BY, (h->nz + BZ - 1) / BZ);
             hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ>), grid, dim3(BX, BY, BZ), 0, h->stream, (const T *)src,
@@ -389,6 +391,13 @@ int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream,
     if (storage < EVLBM_F64 || storage > EVLBM_BF16DEV) return fail(EVLBM_EINVAL, "unknown storage %d", storage);
     if (nx <= 0 || ny <= 0 || nz <= 0) return fail(EVLBM_EINVAL, "lattice sizes must be positive");
     if (lattice == EVLBM_D2Q9 && nz != 1) return fail(EVLBM_EINVAL, "D2Q9 needs nz == 1");
+    {
+        // kernels address a cell of one direction or moment array by a 32-bit byte offset
+        const double cells = (double)nx * ny * nz;
+        const double elem = storage == EVLBM_F64 ? 8.0 : 4.0;  // widest per-cell element of any array
+        if (cells * elem >= 4294967296.0)
+            return fail(EVLBM_EINVAL, "lattice of %.0f cells: each per-direction array must stay below 4 GiB", cells);
+    }
     evlbm_lattice *h = new evlbm_lattice();
     h->D = lattice;
     h->Q = lattice == EVLBM_D2Q9 ? 9 : 27;
@@ -902,28 +911,29 @@ int evlbm_eos_coexistence(double R, double a, double b, double T, double out[3])
 
 namespace evlbm {
 // Plain streaming copy, 16 bytes per thread per iteration, grid-stride.
-__global__ void __launch_bounds__(256) k_copy_probe(const float4 *__restrict__ in, float4 *__restrict__ out, long n)
+typedef float v4f __attribute__((ext_vector_type(4)));
+// one 16-byte element per thread, non-temporal store: the streaming shape
+// that reaches the highest copy rate on this part
+__global__ void __launch_bounds__(256) k_copy_probe(const v4f *__restrict__ in, v4f *__restrict__ out, long n)
 {
-    const long stride = (long)gridDim.x * blockDim.x;
-    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) out[t] = in[t];
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) __builtin_nontemporal_store(in[t], &out[t]);
 }
 }  // namespace evlbm
 
 extern "C" int evlbm_copy_probe(double bytes, int reps, double *gbps_out)
 {
     if (!gbps_out || !(bytes >= 1024) || reps <= 0) return fail(EVLBM_EINVAL, "need bytes >= 1024 and reps > 0");
-    const long n = (long)(bytes / 2 / sizeof(float4));  // half read, half written
-    float4 *a = nullptr, *b = nullptr;
-    hipError_t e = hipMalloc(&a, n * sizeof(float4));
-    if (e == hipSuccess) e = hipMalloc(&b, n * sizeof(float4));
+    const long n = (long)(bytes / 2 / sizeof(v4f));  // half read, half written
+    v4f *a = nullptr, *b = nullptr;
+    hipError_t e = hipMalloc(&a, n * sizeof(v4f));
+    if (e == hipSuccess) e = hipMalloc(&b, n * sizeof(v4f));
     if (e != hipSuccess) {
         if (a) (void)hipFree(a);
         return fail(EVLBM_ENOMEM, "copy probe allocation: %s", hipGetErrorString(e));
     }
-    (void)hipMemset(a, 0, n * sizeof(float4));
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, 0);
-    const int blocks = cus * 8;
+    (void)hipMemset(a, 0, n * sizeof(v4f));
+    const long blocks = (n + 255) / 256;
     hipEvent_t t0, t1;
     (void)hipEventCreate(&t0);
     (void)hipEventCreate(&t1);
@@ -939,6 +949,6 @@ extern "C" int evlbm_copy_probe(double bytes, int reps, double *gbps_out)
     (void)hipFree(a);
     (void)hipFree(b);
     if (e != hipSuccess) return hip_fail(e, "copy probe");
-    *gbps_out = 2.0 * n * sizeof(float4) * reps / (ms * 1e-3) / 1e9;
+    *gbps_out = 2.0 * n * sizeof(v4f) * reps / (ms * 1e-3) / 1e9;
     return EVLBM_OK;
 }

@@ -38,13 +38,9 @@ __host__ __device__ inline int wrapi(int v, int n)
 
 // ------------------------------------------------------------------ codecs
 
-__device__ inline uint16_t f32_to_bf16_rne(float v)
-{
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// gfx950 converts in hardware (v_cvt_pk_bf16_f32): round to nearest even,
+// NaN stays NaN.
+__device__ inline uint16_t f32_to_bf16_rne(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 
 __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
@@ -107,6 +103,61 @@ struct StepParams {
     const float *refrho;  // deviation storage: reference density of every cell (null otherwise)
 };
 
+// ------------------------------------------------------------ addressing
+
+// Every direction array of a lattice holds N cells and is below 4 GiB (the
+// host rejects larger lattices), so a cell is addressed by a uniform 64-bit
+// base (the direction's array, kept in scalar registers) plus a 32-bit byte
+// offset: one vector register per address and the saddr + voffset form of
+// the global loads and stores.
+template <typename T>
+__device__ inline T ld_at(const T *__restrict__ base, unsigned byte)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte);
+}
+
+// Stores of 4- and 8-byte elements are non-temporal: the step's outputs are
+// not re-read before the next launch, so they bypass the caches instead of
+// evicting reused lines.  16-bit elements are stored normally so the L2 can
+// merge them into full lines.
+template <typename T>
+__device__ inline void st_at(T *__restrict__ base, unsigned byte, T v)
+{
+    T *q = reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte);
+    if constexpr (sizeof(T) >= 4)
+        __builtin_nontemporal_store(v, q);
+    else
+        *q = v;
+}
+
+// Byte offsets of the pull sources of a cell in arrays of ES-byte elements:
+// entry k = c + 1 of each axis holds the periodic source coordinate x - c,
+// so direction i reads ox[cx+1] + oy[cy+1] + oz[cz+1].
+struct PullOffsets {
+    unsigned ox[3], oy[3], oz[3];
+};
+
+template <int D, int ES>
+__device__ inline PullOffsets pull_offsets(int nx, int ny, int nz, int x, int y, int z)
+{
+    PullOffsets o;
+    const unsigned sy = (unsigned)nx * ES, sz = (unsigned)nx * (unsigned)ny * ES;
+    o.ox[0] = (unsigned)(x + 1 == nx ? 0 : x + 1) * ES;
+    o.ox[1] = (unsigned)x * ES;
+    o.ox[2] = (unsigned)(x == 0 ? nx - 1 : x - 1) * ES;
+    o.oy[0] = (unsigned)(y + 1 == ny ? 0 : y + 1) * sy;
+    o.oy[1] = (unsigned)y * sy;
+    o.oy[2] = (unsigned)(y == 0 ? ny - 1 : y - 1) * sy;
+    if (D == 3) {
+        o.oz[0] = (unsigned)(z + 1 == nz ? 0 : z + 1) * sz;
+        o.oz[1] = (unsigned)z * sz;
+        o.oz[2] = (unsigned)(z == 0 ? nz - 1 : z - 1) * sz;
+    } else {
+        o.oz[0] = o.oz[1] = o.oz[2] = 0u;
+    }
+    return o;
+}
+
 // Reference value of direction i stored at cell s: refrho[s] * W_i for the
 // 16-bit deviation storage, 0 otherwise.
 template <int S, typename R>
@@ -114,6 +165,16 @@ __device__ inline R ref_at(const StepParams<R> &p, int i, long s)
 {
     if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
         return (R)p.refrho[s] * p.ref[i];
+    else
+        return R(0);
+}
+
+// The same for a cell given by its byte offset in a 16-bit direction array.
+template <int S, typename R>
+__device__ inline R ref_at_b(const StepParams<R> &p, int i, unsigned byte16)
+{
+    if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
+        return (R)ld_at(p.refrho, byte16 * 2u) * p.ref[i];
     else
         return R(0);
 }

@@ -73,17 +73,13 @@ __device__ inline void moments_at(const StoreT<S> *__restrict__ pop, RealT<S> *_
 {
     using R = RealT<S>;
     constexpr int Q = Lat<D>::Q;
-    // source coordinate x - c for c = -1, 0, +1
-    const int xs[3] = {x + 1 == p.nx ? 0 : x + 1, x, x == 0 ? p.nx - 1 : x - 1};
-    const int ys[3] = {y + 1 == p.ny ? 0 : y + 1, y, y == 0 ? p.ny - 1 : y - 1};
-    const int zs[3] = {z + 1 == p.nz ? 0 : z + 1, z, z == 0 ? p.nz - 1 : z - 1};
+    const PullOffsets o = pull_offsets<D, (int)sizeof(StoreT<S>)>(p.nx, p.ny, p.nz, x, y, z);
     R rho = R(0), jx = R(0), jy = R(0), jz = R(0), e = R(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
-        const long src = (long)xs[kx] + (long)p.nx * ((long)ys[ky] + (long)p.ny * zs[kz]);
-        const R f = Codec<S>::dec(pop[(long)i * p.N + src], ref_at<S>(p, i, src));
-        const R g = Codec<S>::dec(pop[(long)(Q + i) * p.N + src], ref_at<S>(p, Q + i, src));
+        const unsigned s = o.ox[cx_of(i) + 1] + o.oy[cy_of(i) + 1] + o.oz[cz_d<D>(i) + 1];
+        const R f = Codec<S>::dec(ld_at(pop + (long)i * p.N, s), ref_at_b<S>(p, i, s));
+        const R g = Codec<S>::dec(ld_at(pop + (long)(Q + i) * p.N, s), ref_at_b<S>(p, Q + i, s));
         rho += f;
         e += g;
         if (cx_of(i) == 1) jx += f;
@@ -93,12 +89,12 @@ __device__ inline void moments_at(const StoreT<S> *__restrict__ pop, RealT<S> *_
         if (cz_d<D>(i) == 1) jz += f;
         if (cz_d<D>(i) == -1) jz -= f;
     }
-    const long cell = (long)x + (long)p.nx * ((long)y + (long)p.ny * z);
-    m[cell] = rho;
-    m[p.N + cell] = jx;
-    m[2 * p.N + cell] = jy;
-    if (D == 3) m[3 * p.N + cell] = jz;
-    m[(D + 1) * p.N + cell] = e;
+    const unsigned c = ((unsigned)x + (unsigned)p.nx * ((unsigned)y + (unsigned)p.ny * (unsigned)z)) * (unsigned)sizeof(R);
+    st_at(m, c, rho);
+    st_at(m + p.N, c, jx);
+    st_at(m + 2 * p.N, c, jy);
+    if (D == 3) st_at(m + 3 * p.N, c, jz);
+    st_at(m + (D + 1) * p.N, c, e);
 }
 
 template <int D, int S>
@@ -110,20 +106,36 @@ __global__ void __launch_bounds__(256) k_moments(const StoreT<S> *__restrict__ p
     moments_at<D, S>(pop, m, p, x, blockIdx.y, blockIdx.z);
 }
 
+// Raw stored values of the pulled populations fh_i(x) = f_i(x - c_i), gh_i
+// likewise, of the cell whose pull sources are o.  Issued as independent
+// loads so a caller can overlap them with other work before decoding.
+template <int D, int S>
+__device__ inline void pull_pops(const StoreT<S> *__restrict__ src, const StepParams<RealT<S>> &p,
+                                 const PullOffsets &o, StoreT<S> fr[], StoreT<S> gr[])
+{
+    constexpr int Q = Lat<D>::Q;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const unsigned s = o.ox[cx_of(i) + 1] + o.oy[cy_of(i) + 1] + o.oz[cz_d<D>(i) + 1];
+        fr[i] = ld_at(src + (long)i * p.N, s);
+        gr[i] = ld_at(src + (long)(Q + i) * p.N, s);
+    }
+}
+
 // Equilibria (eq. feq, f_star, geq, gstar with eq. g_corr), shifted state
 // (eq. def_ustar with Qtilde = 0) and the update eq. pre_LBM for one cell,
-// pulling f, g from src and storing into dst.
+// from its pulled populations (raw stored values fr, gr of pull_pops) into
+// dst at the cell itself (o.ox[1] + o.oy[1] + o.oz[1]).
 template <int D, int S>
-__device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
-                                    const StepParams<RealT<S>> &p, int x, int y, int z, RealT<S> rho,
-                                    RealT<S> inv_rho, RealT<S> K, RealT<S> RT, RealT<S> one_m_br, RealT<S> theta,
-                                    const RealT<S> u[3], const RealT<S> F[3], const RealT<S> Phi[3],
-                                    const RealT<S> qp[3])
+__device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[], StoreT<S> *__restrict__ dst,
+                                      const StepParams<RealT<S>> &p, const PullOffsets &o, RealT<S> rho,
+                                      RealT<S> inv_rho, RealT<S> K, RealT<S> one_m_br, RealT<S> theta,
+                                      const RealT<S> u[3], const RealT<S> F[3], const RealT<S> Phi[3],
+                                      const RealT<S> qp[3])
 {
     using R = RealT<S>;
     constexpr int Q = Lat<D>::Q;
     const long N = p.N;
-    (void)RT;
     // shifted state (eq. def_ustar, Qtilde = 0)
     R us[3], F2 = R(0);
     for (int a = 0; a < 3; ++a) {
@@ -156,11 +168,7 @@ __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S>
     const R hE = K;
     const R omb = R(1) - p.two_beta;
     const R c_eq = p.two_beta - p.wstar;
-
-    const int xs_[3] = {x + 1 == p.nx ? 0 : x + 1, x, x == 0 ? p.nx - 1 : x - 1};
-    const int ys_[3] = {y + 1 == p.ny ? 0 : y + 1, y, y == 0 ? p.ny - 1 : y - 1};
-    const int zs_[3] = {z + 1 == p.nz ? 0 : z + 1, z, z == 0 ? p.nz - 1 : z - 1};
-    const long cell = (long)x + (long)p.nx * ((long)y + (long)p.ny * z);
+    const unsigned cell = o.ox[1] + o.oy[1] + o.oz[1];
 
     // The collision conserves mass and energy exactly: sum f_new = sum fh and
     // sum g_new = sum gh + u.F (eq. pre_LBM with eq. u_shift, T_shift and
@@ -169,16 +177,16 @@ __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S>
     // other directions, so each cell keeps these balances to a single rounding
     // of one stored value and no rounding bias accumulates from step to step.
     constexpr int REST = (Q - 1) / 2;
-    const R fh_rest = Codec<S>::dec(src[(long)REST * N + cell], ref_at<S>(p, REST, cell));
-    const R gh_rest = Codec<S>::dec(src[(long)(Q + REST) * N + cell], ref_at<S>(p, Q + REST, cell));
+    const R fh_rest = Codec<S>::dec(fr[REST], ref_at_b<S>(p, REST, cell));
+    const R gh_rest = Codec<S>::dec(gr[REST], ref_at_b<S>(p, Q + REST, cell));
     double mass = (double)fh_rest, energy = (double)gh_rest, sf = 0.0, sg = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (i == REST) continue;
         const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
-        const long s = (long)xs_[kx] + (long)p.nx * ((long)ys_[ky] + (long)p.ny * zs_[kz]);
-        const R fh = Codec<S>::dec(src[(long)i * N + s], ref_at<S>(p, i, s));
-        const R gh = Codec<S>::dec(src[(long)(Q + i) * N + s], ref_at<S>(p, Q + i, s));
+        const unsigned s = o.ox[kx] + o.oy[ky] + o.oz[kz];
+        const R fh = Codec<S>::dec(fr[i], ref_at_b<S>(p, i, s));
+        const R gh = Codec<S>::dec(gr[i], ref_at_b<S>(p, Q + i, s));
         const R Pyz_e = fe[1][ky] * fe[2][kz];
         const R feq = rho * fe[0][kx] * Pyz_e;
         const R fst = rho * fs[0][kx] * (fs[1][ky] * fs[2][kz]);
@@ -191,19 +199,35 @@ __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S>
         // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq)
         const R fn = omb * fh + c_eq * feq + p.wstar * fst;
         const R gn = omb * gh + c_eq * geq + p.wstar * gst;
-        const R rf = ref_at<S>(p, i, cell), rg = ref_at<S>(p, Q + i, cell);
+        const R rf = ref_at_b<S>(p, i, cell), rg = ref_at_b<S>(p, Q + i, cell);
         const StoreT<S> fq = Codec<S>::enc(fn, rf);
         const StoreT<S> gq = Codec<S>::enc(gn, rg);
-        dst[(long)i * N + cell] = fq;
-        dst[(long)(Q + i) * N + cell] = gq;
+        st_at(dst + (long)i * N, cell, fq);
+        st_at(dst + (long)(Q + i) * N, cell, gq);
         mass += (double)fh;
         energy += (double)gh;
         sf += (double)Codec<S>::dec(fq, rf);
         sg += (double)Codec<S>::dec(gq, rg);
     }
     const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
-    dst[(long)REST * N + cell] = Codec<S>::enc((R)(mass - sf), ref_at<S>(p, REST, cell));
-    dst[(long)(Q + REST) * N + cell] = Codec<S>::enc((R)(energy + uF - sg), ref_at<S>(p, Q + REST, cell));
+    st_at(dst + (long)REST * N, cell, Codec<S>::enc((R)(mass - sf), ref_at_b<S>(p, REST, cell)));
+    st_at(dst + (long)(Q + REST) * N, cell, Codec<S>::enc((R)(energy + uF - sg), ref_at_b<S>(p, Q + REST, cell)));
+}
+
+// Pull and collide one cell (x, y, z) from src into dst.
+template <int D, int S>
+__device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
+                                    const StepParams<RealT<S>> &p, int x, int y, int z, RealT<S> rho,
+                                    RealT<S> inv_rho, RealT<S> K, RealT<S> RT, RealT<S> one_m_br, RealT<S> theta,
+                                    const RealT<S> u[3], const RealT<S> F[3], const RealT<S> Phi[3],
+                                    const RealT<S> qp[3])
+{
+    constexpr int Q = Lat<D>::Q;
+    (void)RT;
+    const PullOffsets o = pull_offsets<D, (int)sizeof(StoreT<S>)>(p.nx, p.ny, p.nz, x, y, z);
+    StoreT<S> fr[Q], gr[Q];
+    pull_pops<D, S>(src, p, o, fr, gr);
+    collide_pulled<D, S>(fr, gr, dst, p, o, rho, inv_rho, K, one_m_br, theta, u, F, Phi, qp);
 }
 
 // ------------------------------------------------------------ k_collide
@@ -425,44 +449,116 @@ __device__ inline R ring_lap(const R *pm, const R *p0, const R *pp, int c, int s
 
 __device__ inline int ring_slot(int k, int n) { return (k + 8 * n) % n; }
 
+// Tile of block b when workgroups are dealt round-robin to the 8 XCDs (each
+// with its own L2): XCD j gets a contiguous run of tiles, x fastest, so
+// tiles that share halo cache lines are resident on the same L2 at the same
+// time.  A bijection of [0, G) for any G.
+__device__ inline int xcd_tile(int b, int G)
+{
+    const int per = G >> 3, rem = G & 7, j = b & 7;
+    return j * per + min(j, rem) + (b >> 3);
+}
+
 template <int S, int TX, int TY, int ZC>
 __global__ void __launch_bounds__(TX *TY)
     k_collide_zm(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
-                 StepParams<RealT<S>> p)
+                 StepParams<RealT<S>> p, int nbx, int nby)
 {
     using R = RealT<S>;
+    using T = StoreT<S>;
     using ZT = ZTile<TX, TY>;
     constexpr int Q = 27;
     constexpr int D = 3;
     constexpr int FU = 0, FM = 3, FTD = 6;
+    constexpr int NR3 = (ZT::N3 + ZT::NT - 1) / ZT::NT;  // rho halo values loaded per thread
+    constexpr int NR1 = (ZT::N1 + ZT::NT - 1) / ZT::NT;  // field cells per thread
+    constexpr unsigned RS = sizeof(R);
     __shared__ R s_rho[ZT::NRHO][ZT::N3];
     __shared__ R s_lap[ZT::NLAP][ZT::N2];
     __shared__ R s_fld[ZT::NFLD][ZT::NF][ZT::N1];
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + TX * ty;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int z0 = blockIdx.z * ZC;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % nbx) * TX, y0 = ((tile / nbx) % nby) * TY;
+    const int z0 = (tile / (nbx * nby)) * ZC;
     const int z1 = min(z0 + ZC, p.nz);
     const long N = p.N;
-    const long plane = (long)p.nx * p.ny;
+    const unsigned plane = (unsigned)p.nx * (unsigned)p.ny;
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < p.nx && y < p.ny;
     // F and K = (3/2) RT of this thread's own column at planes k (cur) and k+1 (nxt)
     R Fc[3] = {R(0), R(0), R(0)}, Kc = R(0), Fn[3] = {R(0), R(0), R(0)}, Kn = R(0);
 
+    // in-plane offset (elements) of the halo cells this thread loads
+    unsigned o3[NR3];
+#pragma unroll
+    for (int j = 0; j < NR3; ++j) {
+        const int t = min(tid + j * ZT::NT, ZT::N3 - 1);
+        const int lx = t % ZT::R3X, ly = t / ZT::R3X;
+        o3[j] = (unsigned)wrapi(x0 + lx - 3, p.nx) + (unsigned)p.nx * (unsigned)wrapi(y0 + ly - 3, p.ny);
+    }
+    // field cells of this thread on tile + 1: interior first (thread tid owns
+    // cell (tx, ty)), then the ring: rows 0 and R1Y-1, then columns 0 and R1X-1
+    int l1x[NR1], l1y[NR1];
+    unsigned o1[NR1];
+#pragma unroll
+    for (int j = 0; j < NR1; ++j) {
+        const int t = min(tid + j * ZT::NT, ZT::N1 - 1);
+        int lx, ly;
+        if (t < ZT::NT) {
+            lx = t % TX + 1;
+            ly = t / TX + 1;
+        } else {
+            const int r = t - ZT::NT;
+            if (r < 2 * ZT::R1X) {
+                lx = r % ZT::R1X;
+                ly = (r < ZT::R1X) ? 0 : ZT::R1Y - 1;
+            } else {
+                const int q = r - 2 * ZT::R1X;
+                lx = (q < TY) ? 0 : ZT::R1X - 1;
+                ly = q % TY + 1;
+            }
+        }
+        l1x[j] = lx;
+        l1y[j] = ly;
+        o1[j] = (unsigned)wrapi(x0 + lx - 1, p.nx) + (unsigned)p.nx * (unsigned)wrapi(y0 + ly - 1, p.ny);
+    }
+
     // Collision of plane z0 needs the fields of planes z0-1..z0+1, hence lap
     // rho of z0-2..z0+2 and rho of z0-3..z0+3: the pipeline starts 6 planes early.
     for (int k = z0 - 6; k < z1; ++k) {
+        const bool col = k >= z0 && active;
+        // (0) issue every global load of this iteration up front, oldest use
+        // first: rho of plane k+3, j and e of plane k+1, the populations of
+        // plane k; stages (1)-(3) then run while the populations are in flight
+        R rv[NR3], mv[NR1][4];
+        {
+            const unsigned zo = (unsigned)wrapi(k + 3, p.nz) * plane;
+#pragma unroll
+            for (int j = 0; j < NR3; ++j)
+                if (tid + j * ZT::NT < ZT::N3) rv[j] = ld_at(m, (o3[j] + zo) * RS);
+        }
+        {
+            const unsigned zo = (unsigned)wrapi(k + 1, p.nz) * plane;
+#pragma unroll
+            for (int j = 0; j < NR1; ++j)
+                if (tid + j * ZT::NT < ZT::N1)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) mv[j][a] = ld_at(m + (a + 1) * N, (o1[j] + zo) * RS);
+        }
+        T fr[Q], gr[Q];
+        PullOffsets po;
+        if (col) {
+            po = pull_offsets<3, (int)sizeof(T)>(p.nx, p.ny, p.nz, x, y, k);
+            pull_pops<3, S>(src, p, po, fr, gr);
+        }
         // (1) rho of plane k + 3 on tile + 3
         {
-            const int zz = wrapi(k + 3, p.nz);
             R *dstp = s_rho[ring_slot(k + 3, ZT::NRHO)];
-            for (int t = tid; t < ZT::N3; t += ZT::NT) {
-                const int lx = t % ZT::R3X, ly = t / ZT::R3X;
-                const int gx = wrapi(x0 + lx - 3, p.nx), gy = wrapi(y0 + ly - 3, p.ny);
-                dstp[t] = m[(long)gx + (long)p.nx * gy + plane * zz];
-            }
+#pragma unroll
+            for (int j = 0; j < NR3; ++j)
+                if (tid + j * ZT::NT < ZT::N3) dstp[tid + j * ZT::NT] = rv[j];
         }
         __syncthreads();
         // (2) lap rho of plane k + 2 on tile + 2
@@ -478,29 +574,15 @@ __global__ void __launch_bounds__(TX *TY)
         __syncthreads();
         // (3) force and half-step fields of plane k + 1 on tile + 1
         {
-            const int zz = wrapi(k + 1, p.nz);
             const R *ra = s_rho[ring_slot(k, ZT::NRHO)], *rb = s_rho[ring_slot(k + 1, ZT::NRHO)],
                     *rc = s_rho[ring_slot(k + 2, ZT::NRHO)];
             const R *la = s_lap[ring_slot(k, ZT::NLAP)], *lb = s_lap[ring_slot(k + 1, ZT::NLAP)],
                     *lc = s_lap[ring_slot(k + 2, ZT::NLAP)];
             R(*fd)[ZT::N1] = s_fld[ring_slot(k + 1, ZT::NFLD)];
-            // interior cells first (thread tid owns cell (tx, ty)), then the ring
-            for (int t = tid; t < ZT::N1; t += ZT::NT) {
-                int lx, ly;
-                if (t < ZT::NT) {
-                    lx = t % TX + 1;
-                    ly = t / TX + 1;
-                } else {
-                    const int r = t - ZT::NT;  // ring cells: rows 0 and R1Y-1, then columns 0 and R1X-1
-                    if (r < 2 * ZT::R1X) {
-                        lx = r % ZT::R1X;
-                        ly = (r < ZT::R1X) ? 0 : ZT::R1Y - 1;
-                    } else {
-                        const int q = r - 2 * ZT::R1X;
-                        lx = (q < TY) ? 0 : ZT::R1X - 1;
-                        ly = q % TY + 1;
-                    }
-                }
+#pragma unroll
+            for (int j = 0; j < NR1; ++j) {
+                if (tid + j * ZT::NT >= ZT::N1) continue;
+                const int lx = l1x[j], ly = l1y[j];
                 const int c3 = (lx + 2) + ZT::R3X * (ly + 2);
                 const int c2 = (lx + 1) + ZT::R2X * (ly + 1);
                 const R rho = rb[c3];
@@ -508,16 +590,14 @@ __global__ void __launch_bounds__(TX *TY)
                 F[0] = p.a * ring_grad_sq<0, R>(ra, rb, rc, c3, ZT::R3X) + p.kappa * rho * ring_grad<0, R>(la, lb, lc, c2, ZT::R2X);
                 F[1] = p.a * ring_grad_sq<1, R>(ra, rb, rc, c3, ZT::R3X) + p.kappa * rho * ring_grad<1, R>(la, lb, lc, c2, ZT::R2X);
                 F[2] = p.a * ring_grad_sq<2, R>(ra, rb, rc, c3, ZT::R3X) + p.kappa * rho * ring_grad<2, R>(la, lb, lc, c2, ZT::R2X);
-                const int gx = wrapi(x0 + lx - 1, p.nx), gy = wrapi(y0 + ly - 1, p.ny);
-                const long cell = (long)gx + (long)p.nx * gy + plane * zz;
                 R u[3], uF = R(0), u2 = R(0);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    u[a] = (m[(a + 1) * N + cell] + R(0.5) * F[a]) / rho;
+                    u[a] = (mv[j][a] + R(0.5) * F[a]) / rho;
                     uF += u[a] * F[a];
                     u2 += u[a] * u[a];
                 }
-                const R K = (m[4 * N + cell] + R(0.5) * uF) / rho - R(0.5) * u2;
+                const R K = (mv[j][3] + R(0.5) * uF) / rho - R(0.5) * u2;
                 const R RT = K * (R(2) / R(3));
                 const R theta = RT / (R(1) - p.b * rho);
                 const int c1 = lx + ZT::R1X * ly;
@@ -527,7 +607,7 @@ __global__ void __launch_bounds__(TX *TY)
                     fd[FM + a][c1] = rho * u[a] * (u[a] * u[a] + R(3) * theta - R(1));
                 }
                 fd[FTD][c1] = theta - RT;
-                if (t < ZT::NT) {
+                if (j == 0) {  // tid < NT: the thread's own column
                     Fn[0] = F[0];
                     Fn[1] = F[1];
                     Fn[2] = F[2];
@@ -537,8 +617,7 @@ __global__ void __launch_bounds__(TX *TY)
         }
         __syncthreads();
         // (4) collide plane k
-        if (k >= z0 && active) {
-            const int z = k;
+        if (col) {
             const R *fm[ZT::NF], *f0[ZT::NF], *fp[ZT::NF];
 #pragma unroll
             for (int q = 0; q < ZT::NF; ++q) {
@@ -571,7 +650,7 @@ __global__ void __launch_bounds__(TX *TY)
             qp[0] = p.lambda * (P0 * ring_grad<0, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[0] * Phip);
             qp[1] = p.lambda * (P0 * ring_grad<1, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[1] * Phip);
             qp[2] = p.lambda * (P0 * ring_grad<2, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[2] * Phip);
-            collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, one_m_br, theta, u, F, Phi, qp);
+            collide_pulled<D, S>(fr, gr, dst, p, po, rho, inv_rho, K, one_m_br, theta, u, F, Phi, qp);
         }
         // rotate the column's F, K
 #pragma unroll
