@@ -235,6 +235,22 @@ class Lattice:
         lib().evo_set_pops(self._h, _p(f), _p(g))
 
 
+def step_window(D, wf, wg, params, radius=4):
+    """One oracle step of a periodic (2*radius+1)-wide window of stored
+    populations wf, wg ([Q, W, W, W] in 3D, [Q, 1, W, W] in 2D); returns the
+    new populations (f[Q], g[Q]) of the window's centre cell, which are exact
+    for the large lattice the window was cut from (see step_sampled)."""
+    W = 2 * radius + 1
+    L = Lattice(3, W, W, W) if D == 3 else Lattice(2, W, W, 1)
+    L.set_params(**params)
+    L.set_pops(np.ascontiguousarray(wf, dtype=np.float64), np.ascontiguousarray(wg, dtype=np.float64))
+    L.step(1)
+    nf, ng = L.get_pops()
+    if D == 3:
+        return nf[:, radius, radius, radius].copy(), ng[:, radius, radius, radius].copy()
+    return nf[:, 0, radius, radius].copy(), ng[:, 0, radius, radius].copy()
+
+
 def step_sampled(D, f, g, cells, params, radius=4):
     """One oracle step evaluated at selected cells of a large periodic lattice.
 
@@ -254,19 +270,10 @@ def step_sampled(D, f, g, cells, params, radius=4):
             zs = (np.arange(W) - radius + z) % nz
             wf = f[:, zs][:, :, ys][:, :, :, xs]
             wg = g[:, zs][:, :, ys][:, :, :, xs]
-            L = Lattice(3, W, W, W)
         else:
             wf = f[:, 0][:, ys][:, :, xs][:, None]
             wg = g[:, 0][:, ys][:, :, xs][:, None]
-            L = Lattice(2, W, W, 1)
-        L.set_params(**params)
-        L.set_pops(wf, wg)
-        L.step(1)
-        nf, ng = L.get_pops()
-        if D == 3:
-            out_f.append(nf[:, radius, radius, radius].copy())
-            out_g.append(ng[:, radius, radius, radius].copy())
-        else:
-            out_f.append(nf[:, 0, radius, radius].copy())
-            out_g.append(ng[:, 0, radius, radius].copy())
+        nf, ng = step_window(D, wf, wg, params, radius)
+        out_f.append(nf)
+        out_g.append(ng)
     return np.array(out_f), np.array(out_g)

@@ -247,10 +247,20 @@ class Lattice:
         _check(lib().evlbm_measure(self._h, MEASURE_DROPLET, g.ctypes.data_as(_dp), out.ctypes.data_as(_dp)))
         return out
 
-    def get_populations(self):
-        f = np.zeros((self.Q,) + self.shape)
-        g = np.zeros((self.Q,) + self.shape)
-        _check(lib().evlbm_get_populations(self._h, _ptr(f), _ptr(g), HOST_F64))
+    def get_populations(self, device=False):
+        """Decoded populations (f, g), each [Q, nz, ny, nx] FP64: numpy arrays,
+        or torch tensors on the lattice's device with device=True."""
+        if not device:
+            f = np.zeros((self.Q,) + self.shape)
+            g = np.zeros((self.Q,) + self.shape)
+            _check(lib().evlbm_get_populations(self._h, _ptr(f), _ptr(g), HOST_F64))
+            return f, g
+        import torch
+        with torch.cuda.stream(self.stream):
+            f = torch.empty((self.Q,) + self.shape, dtype=torch.float64, device="cuda")
+            g = torch.empty((self.Q,) + self.shape, dtype=torch.float64, device="cuda")
+        _check(lib().evlbm_get_populations(self._h, _ptr(f), _ptr(g), DEVICE_F64))
+        torch.cuda.current_stream().wait_stream(self.stream)
         return f, g
 
     def set_populations(self, f, g):

@@ -42,6 +42,7 @@ __device__ inline StepParams<R> domain_params(const StepParams<R> &p, const Doma
     q.ny = d.ny;
     q.nz = 1;
     q.N = d.N;
+    q.ds = d.N;  // a domain's direction arrays are dense in the arena
     q.refrho = p.refrho ? p.refrho + d.cell_off : nullptr;
     return q;
 }
@@ -145,6 +146,7 @@ StepParams<R> dparams(const evlbm_batch *b, int k)
     p.ny = d.ny;
     p.nz = 1;
     p.N = d.N;
+    p.ds = d.N;
     p.refrho = b->refrho ? b->refrho + d.cell_off : nullptr;
     return p;
 }

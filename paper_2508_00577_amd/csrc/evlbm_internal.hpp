@@ -9,9 +9,10 @@
 struct evlbm_lattice {
     int D = 2, Q = 9, nx = 0, ny = 0, nz = 0, storage = EVLBM_F32;
     long N = 0;
+    long ds = 0;                        // direction stride of the population buffers (elements)
     int device = 0;
     hipStream_t stream = nullptr;
-    void *buf[2] = {nullptr, nullptr};  // population buffers, f then g, [2Q][N]
+    void *buf[2] = {nullptr, nullptr};  // population buffers, f then g: 2Q arrays of N cells, ds apart
     int cur = 0;                        // buffer holding the current state
     void *m = nullptr;                  // pulled moments rho, j (D), e: [(D+2)][N]
     void *lap = nullptr;                // readout scratch: lap rho [N]

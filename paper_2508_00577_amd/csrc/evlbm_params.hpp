@@ -15,6 +15,7 @@ inline StepParams<R> model_params(int D, int storage, double Rg, double a, doubl
     StepParams<R> p;
     p.nx = p.ny = p.nz = 1;
     p.N = 1;
+    p.ds = 1;
     p.a = (R)a;
     p.b = (R)b;
     p.kappa = (R)kappa;

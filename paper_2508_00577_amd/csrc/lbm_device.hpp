@@ -93,7 +93,8 @@ struct Codec<EVLBM_BF16DEV> {
 template <typename R>
 struct StepParams {
     int nx, ny, nz;
-    long N;
+    long N;          // cells
+    long ds;         // elements between consecutive direction arrays of the populations (>= N)
     R a, b, kappa;   // EOS: P_E = rho RT/(1 - b rho), P_V = -a rho^2, capillarity
     R two_beta;      // 2 beta, beta = 1/(2 tau + 1)
     R wstar;         // (dt/lambda)(1 - beta)
@@ -129,6 +130,89 @@ __device__ inline void st_at(T *__restrict__ base, unsigned byte, T v)
     else
         *q = v;
 }
+
+// Reciprocal for the per-cell 1/rho and 1/(1 - b rho): the hardware
+// approximation (<= 1 ulp) in FP32, an exact division in FP64.
+template <typename R>
+__device__ inline R rcp(R x)
+{
+    if constexpr (sizeof(R) == 4)
+        return __builtin_amdgcn_rcpf(x);
+    else
+        return R(1) / x;
+}
+
+// Population access through per-direction pointers: array p (0..2Q-1: f
+// directions, then g) of src or dst at a byte offset.
+template <typename T>
+struct PtrPops {
+    const T *src;
+    T *dst;
+    long ds;  // direction stride (elements)
+    __device__ inline T ld(int pop, unsigned byte) const { return ld_at(src + (long)pop * ds, byte); }
+    __device__ inline void st(int pop, unsigned byte, T v) const { st_at(dst + (long)pop * ds, byte, v); }
+};
+
+// Population access through raw buffer resources: one resource per
+// population (f, g) of src and dst, the direction's offset i * ds * sizeof(T)
+// in a scalar register shared by all four, the cell's byte offset in a vector
+// register.  This keeps the 4Q per-direction base pointers of a D3Q27 step
+// out of the scalar register file, which otherwise spills them to vector
+// lanes.  Valid while Q * ds * sizeof(T) < 2^32 (the launcher checks), so
+// that every offset sum stays below 2^32.
+constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, 32-bit data, gfx9 family
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, -1, RSRC_WORD3);
+}
+
+template <typename T>
+__device__ inline T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    if constexpr (sizeof(T) == 2)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, 0));
+    else if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+// Stores of 4- and 8-byte elements carry the non-temporal hint (cache policy
+// bit 1), as st_at does.
+template <typename T>
+__device__ inline void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, T v)
+{
+    if constexpr (sizeof(T) == 2)
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)voff, (int)soff, 0);
+    else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 2);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                              (int)voff, (int)soff, 2);
+}
+
+template <typename T, int Q>
+struct BufPops {
+    __amdgpu_buffer_rsrc_t sf, sg, df, dg;
+    unsigned dir;  // bytes between consecutive direction arrays: ds * sizeof(T)
+    __device__ inline BufPops(const T *src, T *dst, long ds)
+        : sf(make_rsrc(src)), sg(make_rsrc(src + (long)Q * ds)), df(make_rsrc(dst)), dg(make_rsrc(dst + (long)Q * ds)),
+          dir((unsigned)ds * (unsigned)sizeof(T))
+    {
+    }
+    __device__ inline T ld(int pop, unsigned byte) const
+    {
+        return pop < Q ? buf_ld<T>(sf, byte, (unsigned)pop * dir) : buf_ld<T>(sg, byte, (unsigned)(pop - Q) * dir);
+    }
+    __device__ inline void st(int pop, unsigned byte, T v) const
+    {
+        if (pop < Q)
+            buf_st<T>(df, byte, (unsigned)pop * dir, v);
+        else
+            buf_st<T>(dg, byte, (unsigned)(pop - Q) * dir, v);
+    }
+};
 
 // Byte offsets of the pull sources of a cell in arrays of ES-byte elements:
 // entry k = c + 1 of each axis holds the periodic source coordinate x - c,

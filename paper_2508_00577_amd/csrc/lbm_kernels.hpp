@@ -12,6 +12,8 @@
 //              (H7), relax (H8) and store (H9).
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_device.hpp"
 
 namespace evlbm {
@@ -58,8 +60,8 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, c
         const double f = rho * fe[0][kx] * fe[1][ky] * fe[2][kz];
         const double g = rho * ((h * fe[0][kx] + xe[0][kx]) * fe[1][ky] * fe[2][kz] +
                                 fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
-        pop[(long)i * p.N + cell] = Codec<S>::enc((R)f, ref_at<S>(p, i, cell));
-        pop[(long)(Q + i) * p.N + cell] = Codec<S>::enc((R)g, ref_at<S>(p, Q + i, cell));
+        pop[(long)i * p.ds + cell] = Codec<S>::enc((R)f, ref_at<S>(p, i, cell));
+        pop[(long)(Q + i) * p.ds + cell] = Codec<S>::enc((R)g, ref_at<S>(p, Q + i, cell));
     }
 }
 
@@ -78,8 +80,8 @@ __device__ inline void moments_at(const StoreT<S> *__restrict__ pop, RealT<S> *_
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const unsigned s = o.ox[cx_of(i) + 1] + o.oy[cy_of(i) + 1] + o.oz[cz_d<D>(i) + 1];
-        const R f = Codec<S>::dec(ld_at(pop + (long)i * p.N, s), ref_at_b<S>(p, i, s));
-        const R g = Codec<S>::dec(ld_at(pop + (long)(Q + i) * p.N, s), ref_at_b<S>(p, Q + i, s));
+        const R f = Codec<S>::dec(ld_at(pop + (long)i * p.ds, s), ref_at_b<S>(p, i, s));
+        const R g = Codec<S>::dec(ld_at(pop + (long)(Q + i) * p.ds, s), ref_at_b<S>(p, Q + i, s));
         rho += f;
         e += g;
         if (cx_of(i) == 1) jx += f;
@@ -107,35 +109,35 @@ __global__ void __launch_bounds__(256) k_moments(const StoreT<S> *__restrict__ p
 }
 
 // Raw stored values of the pulled populations fh_i(x) = f_i(x - c_i), gh_i
-// likewise, of the cell whose pull sources are o.  Issued as independent
-// loads so a caller can overlap them with other work before decoding.
-template <int D, int S>
-__device__ inline void pull_pops(const StoreT<S> *__restrict__ src, const StepParams<RealT<S>> &p,
-                                 const PullOffsets &o, StoreT<S> fr[], StoreT<S> gr[])
+// likewise, of the cell whose pull sources are o, through the population
+// accessor (PtrPops or BufPops).  Issued as independent loads so a caller can
+// overlap them with other work before decoding.
+template <int D, int S, class A>
+__device__ inline void pull_pops(const A &pops, const PullOffsets &o, StoreT<S> fr[], StoreT<S> gr[])
 {
     constexpr int Q = Lat<D>::Q;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const unsigned s = o.ox[cx_of(i) + 1] + o.oy[cy_of(i) + 1] + o.oz[cz_d<D>(i) + 1];
-        fr[i] = ld_at(src + (long)i * p.N, s);
-        gr[i] = ld_at(src + (long)(Q + i) * p.N, s);
+        fr[i] = pops.ld(i, s);
+        gr[i] = pops.ld(Q + i, s);
     }
 }
 
 // Equilibria (eq. feq, f_star, geq, gstar with eq. g_corr), shifted state
 // (eq. def_ustar with Qtilde = 0) and the update eq. pre_LBM for one cell,
 // from its pulled populations (raw stored values fr, gr of pull_pops) into
-// dst at the cell itself (o.ox[1] + o.oy[1] + o.oz[1]).
-template <int D, int S>
-__device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[], StoreT<S> *__restrict__ dst,
+// the destination of the accessor at the cell itself (o.ox[1] + o.oy[1] +
+// o.oz[1]).  inv_omb = 1/(1 - b rho).
+template <int D, int S, class A>
+__device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[], const A &pops,
                                       const StepParams<RealT<S>> &p, const PullOffsets &o, RealT<S> rho,
-                                      RealT<S> inv_rho, RealT<S> K, RealT<S> one_m_br, RealT<S> theta,
+                                      RealT<S> inv_rho, RealT<S> K, RealT<S> inv_omb, RealT<S> theta,
                                       const RealT<S> u[3], const RealT<S> F[3], const RealT<S> Phi[3],
                                       const RealT<S> qp[3])
 {
     using R = RealT<S>;
     constexpr int Q = Lat<D>::Q;
-    const long N = p.N;
     // shifted state (eq. def_ustar, Qtilde = 0)
     R us[3], F2 = R(0);
     for (int a = 0; a < 3; ++a) {
@@ -145,7 +147,7 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
     // (3/2) RT* = (3/2) RT - lambda^2 |F|^2/(2 rho^2)
     const R hS = K - R(0.5) * p.lambda * p.lambda * F2 * inv_rho * inv_rho;
     const R RTs = hS * (R(2) / R(3));
-    const R thetas = RTs / one_m_br;
+    const R thetas = RTs * inv_omb;
 
     // per-axis factors: fe (f^eq and g^eq), fs (f*), gs (g*), chi for g^eq, g*
     R fe[3][3], fs[3][3], gs[3][3], xe[3][3], xs[3][3];
@@ -202,32 +204,33 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
         const R rf = ref_at_b<S>(p, i, cell), rg = ref_at_b<S>(p, Q + i, cell);
         const StoreT<S> fq = Codec<S>::enc(fn, rf);
         const StoreT<S> gq = Codec<S>::enc(gn, rg);
-        st_at(dst + (long)i * N, cell, fq);
-        st_at(dst + (long)(Q + i) * N, cell, gq);
+        pops.st(i, cell, fq);
+        pops.st(Q + i, cell, gq);
         mass += (double)fh;
         energy += (double)gh;
         sf += (double)Codec<S>::dec(fq, rf);
         sg += (double)Codec<S>::dec(gq, rg);
     }
     const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
-    st_at(dst + (long)REST * N, cell, Codec<S>::enc((R)(mass - sf), ref_at_b<S>(p, REST, cell)));
-    st_at(dst + (long)(Q + REST) * N, cell, Codec<S>::enc((R)(energy + uF - sg), ref_at_b<S>(p, Q + REST, cell)));
+    pops.st(REST, cell, Codec<S>::enc((R)(mass - sf), ref_at_b<S>(p, REST, cell)));
+    pops.st(Q + REST, cell, Codec<S>::enc((R)(energy + uF - sg), ref_at_b<S>(p, Q + REST, cell)));
 }
 
 // Pull and collide one cell (x, y, z) from src into dst.
 template <int D, int S>
 __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
                                     const StepParams<RealT<S>> &p, int x, int y, int z, RealT<S> rho,
-                                    RealT<S> inv_rho, RealT<S> K, RealT<S> RT, RealT<S> one_m_br, RealT<S> theta,
+                                    RealT<S> inv_rho, RealT<S> K, RealT<S> RT, RealT<S> inv_omb, RealT<S> theta,
                                     const RealT<S> u[3], const RealT<S> F[3], const RealT<S> Phi[3],
                                     const RealT<S> qp[3])
 {
     constexpr int Q = Lat<D>::Q;
     (void)RT;
     const PullOffsets o = pull_offsets<D, (int)sizeof(StoreT<S>)>(p.nx, p.ny, p.nz, x, y, z);
+    const PtrPops<StoreT<S>> pops{src, dst, p.ds};
     StoreT<S> fr[Q], gr[Q];
-    pull_pops<D, S>(src, p, o, fr, gr);
-    collide_pulled<D, S>(fr, gr, dst, p, o, rho, inv_rho, K, one_m_br, theta, u, F, Phi, qp);
+    pull_pops<D, S>(pops, o, fr, gr);
+    collide_pulled<D, S>(fr, gr, pops, p, o, rho, inv_rho, K, inv_omb, theta, u, F, Phi, qp);
 }
 
 // ------------------------------------------------------------ k_collide
@@ -299,18 +302,19 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
         const int gx = wrapi(x0 + lx - 1, p.nx), gy = wrapi(y0 + ly - 1, p.ny);
         const int gz = HZ ? wrapi(z0 + lz - 1, p.nz) : 0;
         const long cell = (long)gx + (long)p.nx * ((long)gy + (long)p.ny * gz);
+        const R ir = rcp(rho);
         R u[3], uF = R(0), u2 = R(0);
         for (int a = 0; a < D; ++a) {
-            u[a] = (m[(a + 1) * N + cell] + R(0.5) * F[a]) / rho;
+            u[a] = (m[(a + 1) * N + cell] + R(0.5) * F[a]) * ir;
             uF += u[a] * F[a];
             u2 += u[a] * u[a];
         }
         const R rhoE = m[(D + 1) * N + cell] + R(0.5) * uF;
         // K = (3/2) RT is kept as such: the energy equilibria need (3/2) RT and
         // a round trip through a rounded 2/3 would bias the energy every step.
-        const R K = rhoE / rho - R(0.5) * u2;
+        const R K = rhoE * ir - R(0.5) * u2;
         const R RT = K * (R(2) / R(3));
-        const R theta = RT / (R(1) - p.b * rho);
+        const R theta = RT * rcp(R(1) - p.b * rho);
         for (int a = 0; a < D; ++a) {
             s_f1[(F_U + a) * TS::N1 + t] = u[a];
             s_f1[(F_M + a) * TS::N1 + t] = rho * u[a] * (u[a] * u[a] + R(3) * theta - R(1));
@@ -329,11 +333,11 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
     constexpr int SY = TS::R1X, SZ = TS::R1X * TS::R1Y;
 
     const R rho = s_rho[c3];
-    const R inv_rho = R(1) / rho;
+    const R inv_rho = rcp(rho);
     const R K = s_f1[F_K * TS::N1 + c1];  // (3/2) RT
     const R RT = K * (R(2) / R(3));
-    const R one_m_br = R(1) - p.b * rho;
-    const R theta = RT / one_m_br;
+    const R inv_omb = rcp(R(1) - p.b * rho);
+    const R theta = RT * inv_omb;
     const R P0 = rho * theta;
     R u[3] = {R(0), R(0), R(0)}, F[3] = {R(0), R(0), R(0)};
     for (int a = 0; a < D; ++a) {
@@ -345,7 +349,7 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
     R divu = lds_grad<D, 0, R>(s_f1 + F_U * TS::N1, c1, SY, SZ) +
              lds_grad<D, 1, R>(s_f1 + (F_U + 1) * TS::N1, c1, SY, SZ);
     if (D == 3) divu += lds_grad<D, 2, R>(s_f1 + (F_U + 2) * TS::N1, c1, SY, SZ);
-    const R Phip = P0 * (R(5) / R(3)) * (R(1) - R(1) / one_m_br) * divu;
+    const R Phip = P0 * (R(5) / R(3)) * (R(1) - inv_omb) * divu;
     R Phi[3] = {R(0), R(0), R(0)}, qp[3] = {R(0), R(0), R(0)};
     Phi[0] = p.sphi * lds_grad<D, 0, R>(s_f1 + F_M * TS::N1, c1, SY, SZ) + Phip;
     Phi[1] = p.sphi * lds_grad<D, 1, R>(s_f1 + (F_M + 1) * TS::N1, c1, SY, SZ) + Phip;
@@ -355,7 +359,7 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
         Phi[2] = p.sphi * lds_grad<D, 2, R>(s_f1 + (F_M + 2) * TS::N1, c1, SY, SZ) + Phip;
         qp[2] = p.lambda * (P0 * lds_grad<D, 2, R>(s_f1 + F_TD * TS::N1, c1, SY, SZ) + u[2] * Phip);
     }
-    collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, one_m_br, theta, u, F, Phi, qp);
+    collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, inv_omb, theta, u, F, Phi, qp);
 }
 
 template <int D, int S, int BX, int BY, int BZ>
@@ -449,17 +453,9 @@ __device__ inline R ring_lap(const R *pm, const R *p0, const R *pp, int c, int s
 
 __device__ inline int ring_slot(int k, int n) { return (k + 8 * n) % n; }
 
-// Tile of block b when workgroups are dealt round-robin to the 8 XCDs (each
-// with its own L2): XCD j gets a contiguous run of tiles, x fastest, so
-// tiles that share halo cache lines are resident on the same L2 at the same
-// time.  A bijection of [0, G) for any G.
-__device__ inline int xcd_tile(int b, int G)
-{
-    const int per = G >> 3, rem = G & 7, j = b & 7;
-    return j * per + min(j, rem) + (b >> 3);
-}
-
-template <int S, int TX, int TY, int ZC>
+// BUF selects the population accessor: raw buffer resources (BufPops, valid
+// while 27 N sizeof(T) < 2^32) or per-direction pointers (PtrPops).
+template <int S, int TX, int TY, int ZC, bool BUF>
 __global__ void __launch_bounds__(TX *TY)
     k_collide_zm(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
                  StepParams<RealT<S>> p, int nbx, int nby)
@@ -479,7 +475,7 @@ __global__ void __launch_bounds__(TX *TY)
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + TX * ty;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = blockIdx.x;  // x fastest, then y, then the z chunk
     const int x0 = (tile % nbx) * TX, y0 = ((tile / nbx) % nby) * TY;
     const int z0 = (tile / (nbx * nby)) * ZC;
     const int z1 = min(z0 + ZC, p.nz);
@@ -489,6 +485,8 @@ __global__ void __launch_bounds__(TX *TY)
     const bool active = x < p.nx && y < p.ny;
     // F and K = (3/2) RT of this thread's own column at planes k (cur) and k+1 (nxt)
     R Fc[3] = {R(0), R(0), R(0)}, Kc = R(0), Fn[3] = {R(0), R(0), R(0)}, Kn = R(0);
+    using Pops = typename std::conditional<BUF, BufPops<T, Q>, PtrPops<T>>::type;
+    const Pops pops{src, dst, p.ds};
 
     // in-plane offset (elements) of the halo cells this thread loads
     unsigned o3[NR3];
@@ -525,35 +523,25 @@ __global__ void __launch_bounds__(TX *TY)
         o1[j] = (unsigned)wrapi(x0 + lx - 1, p.nx) + (unsigned)p.nx * (unsigned)wrapi(y0 + ly - 1, p.ny);
     }
 
-    // Collision of plane z0 needs the fields of planes z0-1..z0+1, hence lap
-    // rho of z0-2..z0+2 and rho of z0-3..z0+3: the pipeline starts 6 planes early.
-    for (int k = z0 - 6; k < z1; ++k) {
-        const bool col = k >= z0 && active;
-        // (0) issue every global load of this iteration up front, oldest use
-        // first: rho of plane k+3, j and e of plane k+1, the populations of
-        // plane k; stages (1)-(3) then run while the populations are in flight
-        R rv[NR3], mv[NR1][4];
-        {
-            const unsigned zo = (unsigned)wrapi(k + 3, p.nz) * plane;
+    // Every global load of an iteration is issued up front in straight-line
+    // code (no branch around any of them, so the compiler's wait counters stay
+    // exact), oldest use first: rho of plane k+3, j and e of plane k+1, then
+    // the populations of plane k; stages (1)-(3) run while the populations are
+    // in flight.  Halo loads use clamped offsets; threads past a ragged edge
+    // pull a valid cell and skip only the stores.
+    R rv[NR3], mv[NR1][4];
+    auto load_fields = [&](int k) {
+        const unsigned z3 = (unsigned)wrapi(k + 3, p.nz) * plane, z1 = (unsigned)wrapi(k + 1, p.nz) * plane;
 #pragma unroll
-            for (int j = 0; j < NR3; ++j)
-                if (tid + j * ZT::NT < ZT::N3) rv[j] = ld_at(m, (o3[j] + zo) * RS);
-        }
-        {
-            const unsigned zo = (unsigned)wrapi(k + 1, p.nz) * plane;
+        for (int j = 0; j < NR3; ++j) rv[j] = ld_at(m, (o3[j] + z3) * RS);
 #pragma unroll
-            for (int j = 0; j < NR1; ++j)
-                if (tid + j * ZT::NT < ZT::N1)
+        for (int j = 0; j < NR1; ++j)
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) mv[j][a] = ld_at(m + (a + 1) * N, (o1[j] + zo) * RS);
-        }
-        T fr[Q], gr[Q];
-        PullOffsets po;
-        if (col) {
-            po = pull_offsets<3, (int)sizeof(T)>(p.nx, p.ny, p.nz, x, y, k);
-            pull_pops<3, S>(src, p, po, fr, gr);
-        }
-        // (1) rho of plane k + 3 on tile + 3
+            for (int a = 0; a < 4; ++a) mv[j][a] = ld_at(m + (a + 1) * N, (o1[j] + z1) * RS);
+    };
+    // stages (1)-(3) of iteration k: rho of plane k+3 on tile + 3, lap rho of
+    // plane k+2 on tile + 2, force and half-step fields of plane k+1 on tile + 1
+    auto stencil_stages = [&](int k) {
         {
             R *dstp = s_rho[ring_slot(k + 3, ZT::NRHO)];
 #pragma unroll
@@ -561,7 +549,6 @@ __global__ void __launch_bounds__(TX *TY)
                 if (tid + j * ZT::NT < ZT::N3) dstp[tid + j * ZT::NT] = rv[j];
         }
         __syncthreads();
-        // (2) lap rho of plane k + 2 on tile + 2
         {
             const R *a = s_rho[ring_slot(k + 1, ZT::NRHO)], *b = s_rho[ring_slot(k + 2, ZT::NRHO)],
                     *c = s_rho[ring_slot(k + 3, ZT::NRHO)];
@@ -572,7 +559,6 @@ __global__ void __launch_bounds__(TX *TY)
             }
         }
         __syncthreads();
-        // (3) force and half-step fields of plane k + 1 on tile + 1
         {
             const R *ra = s_rho[ring_slot(k, ZT::NRHO)], *rb = s_rho[ring_slot(k + 1, ZT::NRHO)],
                     *rc = s_rho[ring_slot(k + 2, ZT::NRHO)];
@@ -590,16 +576,17 @@ __global__ void __launch_bounds__(TX *TY)
                 F[0] = p.a * ring_grad_sq<0, R>(ra, rb, rc, c3, ZT::R3X) + p.kappa * rho * ring_grad<0, R>(la, lb, lc, c2, ZT::R2X);
                 F[1] = p.a * ring_grad_sq<1, R>(ra, rb, rc, c3, ZT::R3X) + p.kappa * rho * ring_grad<1, R>(la, lb, lc, c2, ZT::R2X);
                 F[2] = p.a * ring_grad_sq<2, R>(ra, rb, rc, c3, ZT::R3X) + p.kappa * rho * ring_grad<2, R>(la, lb, lc, c2, ZT::R2X);
+                const R ir = rcp(rho);
                 R u[3], uF = R(0), u2 = R(0);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    u[a] = (mv[j][a] + R(0.5) * F[a]) / rho;
+                    u[a] = (mv[j][a] + R(0.5) * F[a]) * ir;
                     uF += u[a] * F[a];
                     u2 += u[a] * u[a];
                 }
-                const R K = (mv[j][3] + R(0.5) * uF) / rho - R(0.5) * u2;
+                const R K = (mv[j][3] + R(0.5) * uF) * ir - R(0.5) * u2;
                 const R RT = K * (R(2) / R(3));
-                const R theta = RT / (R(1) - p.b * rho);
+                const R theta = RT * rcp(R(1) - p.b * rho);
                 const int c1 = lx + ZT::R1X * ly;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -616,8 +603,26 @@ __global__ void __launch_bounds__(TX *TY)
             }
         }
         __syncthreads();
+    };
+
+    // Collision of plane z0 needs the fields of planes z0-1..z0+1, hence lap
+    // rho of z0-2..z0+2 and rho of z0-3..z0+3: the pipeline starts 6 planes early.
+    for (int k = z0 - 6; k < z0; ++k) {
+        load_fields(k);
+        stencil_stages(k);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Fc[a] = Fn[a];
+        Kc = Kn;
+    }
+    const int xl = min(x, p.nx - 1), yl = min(y, p.ny - 1);
+    for (int k = z0; k < z1; ++k) {
+        load_fields(k);
+        T fr[Q], gr[Q];
+        const PullOffsets po = pull_offsets<3, (int)sizeof(T)>(p.nx, p.ny, p.nz, xl, yl, k);
+        pull_pops<3, S>(pops, po, fr, gr);
+        stencil_stages(k);
         // (4) collide plane k
-        if (col) {
+        if (active) {
             const R *fm[ZT::NF], *f0[ZT::NF], *fp[ZT::NF];
 #pragma unroll
             for (int q = 0; q < ZT::NF; ++q) {
@@ -627,11 +632,11 @@ __global__ void __launch_bounds__(TX *TY)
             }
             const int c1 = (tx + 1) + ZT::R1X * (ty + 1);
             const R rho = s_rho[ring_slot(k, ZT::NRHO)][(tx + 3) + ZT::R3X * (ty + 3)];
-            const R inv_rho = R(1) / rho;
+            const R inv_rho = rcp(rho);
             const R K = Kc;
             const R RT = K * (R(2) / R(3));
-            const R one_m_br = R(1) - p.b * rho;
-            const R theta = RT / one_m_br;
+            const R inv_omb = rcp(R(1) - p.b * rho);
+            const R theta = RT * inv_omb;
             const R P0 = rho * theta;
             R u[3], F[3];
 #pragma unroll
@@ -642,7 +647,7 @@ __global__ void __launch_bounds__(TX *TY)
             const R divu = ring_grad<0, R>(fm[FU], f0[FU], fp[FU], c1, ZT::R1X) +
                            ring_grad<1, R>(fm[FU + 1], f0[FU + 1], fp[FU + 1], c1, ZT::R1X) +
                            ring_grad<2, R>(fm[FU + 2], f0[FU + 2], fp[FU + 2], c1, ZT::R1X);
-            const R Phip = P0 * (R(5) / R(3)) * (R(1) - R(1) / one_m_br) * divu;
+            const R Phip = P0 * (R(5) / R(3)) * (R(1) - inv_omb) * divu;
             R Phi[3], qp[3];
             Phi[0] = p.sphi * ring_grad<0, R>(fm[FM], f0[FM], fp[FM], c1, ZT::R1X) + Phip;
             Phi[1] = p.sphi * ring_grad<1, R>(fm[FM + 1], f0[FM + 1], fp[FM + 1], c1, ZT::R1X) + Phip;
@@ -650,7 +655,7 @@ __global__ void __launch_bounds__(TX *TY)
             qp[0] = p.lambda * (P0 * ring_grad<0, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[0] * Phip);
             qp[1] = p.lambda * (P0 * ring_grad<1, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[1] * Phip);
             qp[2] = p.lambda * (P0 * ring_grad<2, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[2] * Phip);
-            collide_pulled<D, S>(fr, gr, dst, p, po, rho, inv_rho, K, one_m_br, theta, u, F, Phi, qp);
+            collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, inv_omb, theta, u, F, Phi, qp);
         }
         // rotate the column's F, K
 #pragma unroll
@@ -821,7 +826,7 @@ __global__ void __launch_bounds__(256) k_sums(const StoreT<S> *__restrict__ pop,
         double fmin_ = 1e300;
         for (int i = 0; i < Q; ++i) {
             const long src = (long)xs[cx_of(i) + 1] + (long)p.nx * ((long)ys[cy_of(i) + 1] + (long)p.ny * zs[cz_d<D>(i) + 1]);
-            const double f = Codec<S>::dec(pop[(long)i * p.N + src], ref_at<S>(p, i, src));
+            const double f = Codec<S>::dec(pop[(long)i * p.ds + src], ref_at<S>(p, i, src));
             fmin_ = fmin(fmin_, f);
         }
         v[7] = fmin_;
@@ -884,7 +889,8 @@ __global__ void __launch_bounds__(256) k_decode(const StoreT<S> *__restrict__ po
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N * Q2) return;
     const int i = (int)(t / N);
-    out[t] = (double)Codec<S>::dec(pop[t], ref_at<S>(p, i, t - (long)i * N));
+    const long c = t - (long)i * N;
+    out[t] = (double)Codec<S>::dec(pop[(long)i * p.ds + c], ref_at<S>(p, i, c));
 }
 
 template <int S>
@@ -894,7 +900,8 @@ __global__ void __launch_bounds__(256) k_encode(const double *__restrict__ in, S
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N * Q2) return;
     const int i = (int)(t / N);
-    pop[t] = Codec<S>::enc((RealT<S>)in[t], ref_at<S>(p, i, t - (long)i * N));
+    const long c = t - (long)i * N;
+    pop[(long)i * p.ds + c] = Codec<S>::enc((RealT<S>)in[t], ref_at<S>(p, i, c));
 }
 
 // Validate initial fields: rho > 0, b rho < 1, T > 0 and finite.
