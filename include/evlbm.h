@@ -45,23 +45,22 @@ enum {
 
 enum { EVLBM_D2Q9 = 2, EVLBM_D3Q27 = 3 };
 
-/* Population storage.  F16DEV/BF16DEV store h_i(x) = f_i(x) - rho_ref(x) W_i
- * in 16 bits (round to nearest even) and decode to FP32 for the arithmetic:
- * W_i is the equilibrium at rest per unit density at the reference state
- * (options EVLBM_OPT_REF_RHO, EVLBM_OPT_REF_T) and rho_ref(x) a per-cell
- * reference density, set to the initial density field (or to the stored
- * density of every cell by a re-reference, EVLBM_OPT_REREF_EVERY). */
+/* Population storage.  F16DEV/BF16DEV store the scaled deviation
+ * h_i(x) = (f_i(x) - f^ref_i(x))/s_i(x) in 16 bits (round to nearest even) and
+ * decode to FP32 for the arithmetic: f^ref, g^ref are the equilibria at rest
+ * (eq. feq, eq. geq with u = 0) of a per-cell reference state (rho_ref,
+ * theta_ref), s = f^ref for f and (3/2) RT_ref f^ref for g.  The reference
+ * state is set from the initial fields and, on a lattice, refreshed from the
+ * stored state of every cell every EVLBM_OPT_REREF_EVERY steps (default 100). */
 enum { EVLBM_F64 = 0, EVLBM_F32 = 1, EVLBM_F16DEV = 2, EVLBM_BF16DEV = 3 };
 
 enum { EVLBM_HOST_F64 = 0, EVLBM_DEVICE_F32 = 1, EVLBM_DEVICE_F64 = 2 };
 
 enum {
     EVLBM_OPT_SPHI = 1,        /* sign in front of the first term of eq. correction_u (default -1) */
-    EVLBM_OPT_REF_RHO = 2,     /* reference density of the 16-bit deviation storage */
-    EVLBM_OPT_REF_T = 3,       /* reference temperature of the 16-bit deviation storage */
     EVLBM_OPT_CHECK_EVERY = 4, /* scan for non-finite densities every K steps (0 = never) */
     EVLBM_OPT_USE_GRAPH = 5,   /* 1: replay step chunks from a captured hipGraph (default 1) */
-    EVLBM_OPT_REREF_EVERY = 6  /* 16-bit storage: re-reference every K steps (0 = never) */
+    EVLBM_OPT_REREF_EVERY = 6  /* 16-bit storage: re-reference every K steps (0 = never; default 100) */
 };
 
 enum { EVLBM_MEASURE_SLAB = 1, EVLBM_MEASURE_DROPLET = 2 };
@@ -184,13 +183,13 @@ typedef struct {
 int evlbm_batch_create(int n, const evlbm_domain_desc *d, int storage, void *stream, evlbm_batch_t *out);
 int evlbm_batch_destroy(evlbm_batch_t b);
 
-/* Shared parameters (as evlbm_set_eos, evlbm_set_relaxation, EVLBM_OPT_SPHI)
- * and the 16-bit storage reference state. */
+/* Shared parameters (as evlbm_set_eos, evlbm_set_relaxation, EVLBM_OPT_SPHI). */
 int evlbm_batch_set_params(evlbm_batch_t b, double R, double a, double bexcl, double kappa, double tau,
                            double lambda, double sphi);
-int evlbm_batch_set_reference(evlbm_batch_t b, double ref_rho, double ref_T);
 
 /* Initialise domain k from host FP64 fields rho[N_k], u[2 N_k] (nullable), T[N_k].
+ * With 16-bit storage the domain's per-cell reference state is taken from
+ * these fields and kept (batched domains are not re-referenced).
  * Errors: EINVAL, ENONPHYS, ENONFINITE. */
 int evlbm_batch_init_domain(evlbm_batch_t b, int k, const double *rho, const double *u, const double *T);
 

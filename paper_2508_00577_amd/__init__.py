@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libevlbm.so")
 D2Q9, D3Q27 = 2, 3
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 HOST_F64, DEVICE_F32, DEVICE_F64 = 0, 1, 2
-OPT_SPHI, OPT_REF_RHO, OPT_REF_T, OPT_CHECK_EVERY, OPT_USE_GRAPH, OPT_REREF_EVERY = 1, 2, 3, 4, 5, 6
+OPT_SPHI, OPT_CHECK_EVERY, OPT_USE_GRAPH, OPT_REREF_EVERY = 1, 4, 5, 6
 MEASURE_SLAB, MEASURE_DROPLET = 1, 2
 STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE", -6: "EIO", -7: "ENONPHYS"}
@@ -73,7 +73,6 @@ def lib():
         L.evlbm_batch_create.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.POINTER(_vp)]
         L.evlbm_batch_destroy.argtypes = [_vp]
         L.evlbm_batch_set_params.argtypes = [_vp] + [ctypes.c_double] * 7
-        L.evlbm_batch_set_reference.argtypes = [_vp, ctypes.c_double, ctypes.c_double]
         L.evlbm_batch_init_domain.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
         L.evlbm_batch_step.argtypes = [_vp, ctypes.c_int64]
         L.evlbm_batch_read.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
@@ -319,9 +318,6 @@ class Batch:
 
     def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0):
         _check(lib().evlbm_batch_set_params(self._h, R, a, b, kappa, tau, lam, sphi))
-
-    def set_reference(self, rho_ref, T_ref):
-        _check(lib().evlbm_batch_set_reference(self._h, float(rho_ref), float(T_ref)))
 
     def init_domain(self, k, rho, T, u=None):
         nx, ny = self.sizes[k]

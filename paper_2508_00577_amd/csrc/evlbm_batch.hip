@@ -43,7 +43,7 @@ __device__ inline StepParams<R> domain_params(const StepParams<R> &p, const Doma
     q.nz = 1;
     q.N = d.N;
     q.ds = d.N;  // a domain's direction arrays are dense in the arena
-    q.refrho = p.refrho ? p.refrho + d.cell_off : nullptr;
+    q.refst = p.refst ? p.refst + d.cell_off : nullptr;
     return q;
 }
 
@@ -86,7 +86,7 @@ struct evlbm_batch {
     void *buf[2] = {nullptr, nullptr};
     void *m = nullptr;
     void *lap = nullptr;
-    float *refrho = nullptr;
+    float2 *refst = nullptr;  // 16-bit storage: reference (rho, theta) per cell of every domain
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     DomainRec *d_dom = nullptr;
@@ -95,7 +95,6 @@ struct evlbm_batch {
     int grid[NVARIANT][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // persistent grid: moments, collide
     int variant = 0;
     double R = 1.0, a = 0.0, b = 0.0, kappa = 0.0, tau = 1.0, lambda = 1.0, sphi = -1.0;
-    double ref_rho = 1.0, ref_T = 0.02;
     int cur = 0;
     int64_t step = 0;
     bool m_valid = false;
@@ -131,9 +130,8 @@ int scratch(evlbm_batch *b, size_t bytes)
 template <typename R>
 StepParams<R> bparams(const evlbm_batch *b)
 {
-    StepParams<R> p = model_params<R>(2, b->storage, b->R, b->a, b->b, b->kappa, b->tau, b->lambda, b->sphi,
-                                      b->ref_rho, b->ref_T);
-    p.refrho = b->refrho;
+    StepParams<R> p = model_params<R>(b->R, b->a, b->b, b->kappa, b->tau, b->lambda, b->sphi);
+    p.refst = b->refst;
     return p;
 }
 
@@ -147,7 +145,7 @@ StepParams<R> dparams(const evlbm_batch *b, int k)
     p.nz = 1;
     p.N = d.N;
     p.ds = d.N;
-    p.refrho = b->refrho ? b->refrho + d.cell_off : nullptr;
+    p.refst = b->refst ? b->refst + d.cell_off : nullptr;
     return p;
 }
 
@@ -215,7 +213,7 @@ struct BDispatchS {
     {
         const DomainRec &d = b->doms[k];
         const long n = d.N * 18;
-        hipLaunchKernelGGL((k_decode<S>), dim3((n + 255) / 256), dim3(256), 0, b->stream,
+        hipLaunchKernelGGL((k_decode<2, S>), dim3((n + 255) / 256), dim3(256), 0, b->stream,
                            (const StoreT<S> *)b->buf[b->cur] + d.pop_off, out, d.N, 18, dparams<RealT<S>>(b, k));
     }
     static void readout(evlbm_batch *b, int k, double *rho, double *u, double *T0)
@@ -300,7 +298,7 @@ int evlbm_batch_destroy(evlbm_batch_t b)
         if (b->buf[k]) (void)hipFree(b->buf[k]);
     if (b->m) (void)hipFree(b->m);
     if (b->lap) (void)hipFree(b->lap);
-    if (b->refrho) (void)hipFree(b->refrho);
+    if (b->refst) (void)hipFree(b->refst);
     if (b->scratch) (void)hipFree(b->scratch);
     if (b->d_dom) (void)hipFree(b->d_dom);
     for (int v = 0; v < NVARIANT; ++v)
@@ -341,7 +339,7 @@ int evlbm_batch_create(int n, const evlbm_domain_desc *d, int storage, void *str
     if (e == hipSuccess) e = hipMalloc(&b->m, (size_t)mo * rbytes(storage));
     if (e == hipSuccess) e = hipMalloc(&b->lap, (size_t)cells * rbytes(storage));
     if (e == hipSuccess && (storage == EVLBM_F16DEV || storage == EVLBM_BF16DEV))
-        e = hipMalloc(&b->refrho, (size_t)cells * sizeof(float));
+        e = hipMalloc(&b->refst, (size_t)cells * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc(&b->d_dom, sizeof(DomainRec) * n);
     if (e == hipSuccess) e = hipMemcpy(b->d_dom, b->doms.data(), sizeof(DomainRec) * n, hipMemcpyHostToDevice);
     // tile lists per compiled shape, domain by domain, row-major tiles
@@ -383,15 +381,6 @@ int evlbm_batch_set_params(evlbm_batch_t b, double R, double a, double bb, doubl
     return EVLBM_OK;
 }
 
-int evlbm_batch_set_reference(evlbm_batch_t b, double ref_rho, double ref_T)
-{
-    if (!b || !(ref_rho > 0) || !(ref_T > 0)) return fail(EVLBM_EINVAL, "need a positive reference state");
-    b->ref_rho = ref_rho;
-    b->ref_T = ref_T;
-    drop_graphs(b);
-    return EVLBM_OK;
-}
-
 int evlbm_batch_init_domain(evlbm_batch_t b, int k, const double *rho, const double *u, const double *T)
 {
     if (!b || k < 0 || k >= b->n || !rho || !T) return fail(EVLBM_EINVAL, "bad domain index or null field");
@@ -408,9 +397,9 @@ int evlbm_batch_init_domain(evlbm_batch_t b, int k, const double *rho, const dou
     if (e == hipSuccess) e = hipMemcpyAsync(dt, T, sizeof(double) * d.N, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, sizeof(double) * 2 * d.N, hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hip_fail(e, "copying initial fields");
-    if (b->refrho)
-        hipLaunchKernelGGL(k_f64_to_f32, dim3((d.N + 255) / 256), dim3(256), 0, b->stream, (const double *)dr,
-                           b->refrho + d.cell_off, d.N);
+    if (b->refst)
+        hipLaunchKernelGGL(k_ref_from_fields, dim3((d.N + 255) / 256), dim3(256), 0, b->stream, (const double *)dr,
+                           (const double *)dt, d.N, b->R, b->b, b->refst + d.cell_off);
     BATCH_DISPATCH(init(b, k, dr, du, dt));
     e = hipStreamSynchronize(b->stream);
     if (e == hipSuccess) e = hipGetLastError();

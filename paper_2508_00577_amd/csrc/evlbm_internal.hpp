@@ -16,14 +16,13 @@ struct evlbm_lattice {
     int cur = 0;                        // buffer holding the current state
     void *m = nullptr;                  // pulled moments rho, j (D), e: [(D+2)][N]
     void *lap = nullptr;                // readout scratch: lap rho [N]
-    float *refrho = nullptr;            // 16-bit deviation storage: reference density per cell [N]
+    float2 *refst = nullptr;            // 16-bit deviation storage: reference (rho, theta) per cell [N]
     void *scratch = nullptr;            // I/O and reduction scratch
     size_t scratch_bytes = 0;
     // model
     double R = 1.0, a = 0.0, b = 0.0, kappa = 0.0, tau = 1.0, lambda = 1.0, sphi = -1.0;
-    double ref_rho = 1.0, ref_T = 0.02;  // deviation-storage reference state
     int64_t check_every = 0;
-    int64_t reref_every = 0;             // 16-bit storage: re-reference period (0 = never)
+    int64_t reref_every = 100;           // 16-bit storage: re-reference period (0 = never)
     bool use_graph = true;
     // state
     int64_t step = 0;

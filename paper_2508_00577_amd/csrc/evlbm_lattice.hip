@@ -42,48 +42,16 @@ size_t store_bytes(int storage) { return storage == EVLBM_F64 ? 8 : storage == E
 static constexpr long DIR_PAD = 1280;
 size_t real_bytes(int storage) { return storage == EVLBM_F64 ? 8 : 4; }
 
-// Reference populations of the 16-bit deviation storage: the equilibrium of
-// a uniform state at rest with density ref_rho and temperature ref_T.
-void reference_populations(int D, double R, double b, double rho, double T, double out[54])
-{
-    const int Q = D == 2 ? 9 : 27;
-    const double RT = R * T;
-    const double theta = RT / (1.0 - b * rho);
-    double fe[3][3], xe[3][3];
-    for (int a = 0; a < 3; ++a) {
-        // at rest: psi(0) = 1 - theta, psi(+-1) = theta/2; chi with u = 0:
-        // chi(0) = -theta^2, chi(+-1) = theta^2/2
-        if (a < D) {
-            fe[a][0] = fe[a][2] = 0.5 * theta;
-            fe[a][1] = 1.0 - theta;
-            xe[a][0] = xe[a][2] = 0.5 * theta * theta;
-            xe[a][1] = -theta * theta;
-        } else {
-            fe[a][0] = fe[a][2] = 0.0;
-            fe[a][1] = 1.0;
-            xe[a][0] = xe[a][1] = xe[a][2] = 0.0;
-        }
-    }
-    for (int i = 0; i < 54; ++i) out[i] = 0.0;
-    for (int i = 0; i < Q; ++i) {
-        const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = (D == 3 ? cz_of(i) : 0) + 1;
-        out[i] = rho * fe[0][kx] * fe[1][ky] * fe[2][kz];
-        out[Q + i] = rho * ((1.5 * RT * fe[0][kx] + xe[0][kx]) * fe[1][ky] * fe[2][kz] +
-                            fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
-    }
-}
-
 template <typename R>
 StepParams<R> make_params(const evlbm_lattice *h)
 {
-    StepParams<R> p = model_params<R>(h->D, h->storage, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi,
-                                      h->ref_rho, h->ref_T);
+    StepParams<R> p = model_params<R>(h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi);
     p.nx = h->nx;
     p.ny = h->ny;
     p.nz = h->nz;
     p.N = h->N;
     p.ds = h->ds;
-    p.refrho = h->refrho;
+    p.refst = h->refst;
     return p;
 }
 
@@ -167,14 +135,25 @@ struct Ops {
     static void decode(evlbm_lattice *h, double *out)
     {
         const long n = h->N * 2 * h->Q;
-        hipLaunchKernelGGL((k_decode<S>), dim3((n + 255) / 256), dim3(256), 0, h->stream, (const T *)h->buf[h->cur],
+        hipLaunchKernelGGL((k_decode<D, S>), dim3((n + 255) / 256), dim3(256), 0, h->stream, (const T *)h->buf[h->cur],
                            out, h->N, 2 * h->Q, make_params<R>(h));
     }
     static void encode(evlbm_lattice *h, const double *in)
     {
         const long n = h->N * 2 * h->Q;
-        hipLaunchKernelGGL((k_encode<S>), dim3((n + 255) / 256), dim3(256), 0, h->stream, in, (T *)h->buf[h->cur],
+        hipLaunchKernelGGL((k_encode<D, S>), dim3((n + 255) / 256), dim3(256), 0, h->stream, in, (T *)h->buf[h->cur],
                            h->N, 2 * h->Q, make_params<R>(h));
+    }
+    static void rereference(evlbm_lattice *h)
+    {
+        if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
+            hipLaunchKernelGGL((k_rereference<D, S>), dim3((h->N + 255) / 256), dim3(256), 0, h->stream,
+                               (T *)h->buf[h->cur], h->refst, make_params<R>(h));
+    }
+    static void ref_from_pops(evlbm_lattice *h, const double *pops)
+    {
+        hipLaunchKernelGGL((k_ref_from_pops<D>), dim3((h->N + 255) / 256), dim3(256), 0, h->stream, pops, h->N,
+                           h->b, h->refst);
     }
     static void scan(evlbm_lattice *h, int *flag)
     {
@@ -238,6 +217,14 @@ struct RunDecode {
 template <int D, int S>
 struct RunEncode {
     static void run(evlbm_lattice *h, const double *i) { Ops<D, S>::encode(h, i); }
+};
+template <int D, int S>
+struct RunReref {
+    static void run(evlbm_lattice *h) { Ops<D, S>::rereference(h); }
+};
+template <int D, int S>
+struct RunRefFromPops {
+    static void run(evlbm_lattice *h, const double *pops) { Ops<D, S>::ref_from_pops(h, pops); }
 };
 template <int D, int S>
 struct RunScan {
@@ -324,18 +311,13 @@ void launch_step(evlbm_lattice *h)
     h->step++;
 }
 
-// 16-bit deviation storage: decode with the current per-cell reference, take
-// the stored density of every cell as the new reference and encode again.
+// 16-bit deviation storage: decode every cell's stored values with its
+// reference state, take the state they carry (rho, theta) as the new
+// reference and encode again, in place.
 int rereference(evlbm_lattice *h)
 {
-    if (!h->refrho) return EVLBM_OK;
-    const size_t half = sizeof(double) * h->N * h->Q;
-    int rc = ensure_scratch(h, 2 * half);
-    if (rc) return rc;
-    dispatch<RunDecode>(h, (double *)h->scratch);
-    hipLaunchKernelGGL(k_refrho_from_pops, dim3((h->N + 255) / 256), dim3(256), 0, h->stream,
-                       (const double *)h->scratch, h->N, h->Q, h->refrho);
-    dispatch<RunEncode>(h, (const double *)h->scratch);
+    if (!h->refst) return EVLBM_OK;
+    dispatch<RunReref>(h);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "re-reference");
     h->m_valid = false;
@@ -437,7 +419,7 @@ int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream,
     e = hipMalloc(&h->m, m_bytes);
     if (e == hipSuccess) e = hipMalloc(&h->lap, (size_t)h->N * real_bytes(storage));
     if (e == hipSuccess && (storage == EVLBM_F16DEV || storage == EVLBM_BF16DEV))
-        e = hipMalloc(&h->refrho, (size_t)h->N * sizeof(float));
+        e = hipMalloc(&h->refst, (size_t)h->N * sizeof(float2));
     if (e != hipSuccess) {
         evlbm_destroy(h);
         return fail(EVLBM_ENOMEM, "hipMalloc for moment fields: %s", hipGetErrorString(e));
@@ -455,7 +437,7 @@ int evlbm_destroy(evlbm_t h)
         if (h->buf[k]) hipFree(h->buf[k]);
     if (h->m) hipFree(h->m);
     if (h->lap) hipFree(h->lap);
-    if (h->refrho) hipFree(h->refrho);
+    if (h->refst) hipFree(h->refst);
     if (h->scratch) hipFree(h->scratch);
     delete h;
     return EVLBM_OK;
@@ -500,16 +482,6 @@ int evlbm_set_option(evlbm_t h, int key, double value)
     case EVLBM_OPT_SPHI:
         if (value != 1.0 && value != -1.0 && value != 0.0) return fail(EVLBM_EINVAL, "s_phi must be -1, 0 or +1");
         h->sphi = value;
-        break;
-    case EVLBM_OPT_REF_RHO:
-        if (!(value > 0)) return fail(EVLBM_EINVAL, "reference density must be positive");
-        if (h->initialized) return fail(EVLBM_ESTATE, "set the deviation reference before initialisation");
-        h->ref_rho = value;
-        break;
-    case EVLBM_OPT_REF_T:
-        if (!(value > 0)) return fail(EVLBM_EINVAL, "reference temperature must be positive");
-        if (h->initialized) return fail(EVLBM_ESTATE, "set the deviation reference before initialisation");
-        h->ref_T = value;
         break;
     case EVLBM_OPT_CHECK_EVERY:
         if (value < 0) return fail(EVLBM_EINVAL, "check interval must be >= 0");
@@ -582,9 +554,9 @@ int evlbm_init_fields(evlbm_t h, const void *rho, const void *u, const void *T, 
         if (host & 1) return fail(EVLBM_ENONPHYS, "need rho > 0, b rho < 1, T > 0 everywhere");
     }
     h->cur = 0;
-    if (h->refrho)
-        hipLaunchKernelGGL(k_f64_to_f32, dim3((N + 255) / 256), dim3(256), 0, h->stream, (const double *)d_rho,
-                           h->refrho, N);
+    if (h->refst)
+        hipLaunchKernelGGL(k_ref_from_fields, dim3((N + 255) / 256), dim3(256), 0, h->stream, (const double *)d_rho,
+                           (const double *)d_T, N, h->R, h->b, h->refst);
     dispatch<RunInit>(h, (const double *)d_rho, (const double *)d_u, (const double *)d_T);
     rc = check_launch("k_init");
     if (rc) return rc;
@@ -604,7 +576,7 @@ int evlbm_step(evlbm_t h, int64_t nsteps)
     if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
     if (nsteps < 0) return fail(EVLBM_EINVAL, "nsteps must be >= 0");
     int64_t done = 0;
-    const int64_t reref = h->refrho ? h->reref_every : 0;
+    const int64_t reref = h->refst ? h->reref_every : 0;
     while (done < nsteps) {
         int64_t chunk = nsteps - done;
         if (h->check_every > 0) chunk = std::min<int64_t>(chunk, h->check_every - (h->step % h->check_every));
@@ -746,9 +718,7 @@ int evlbm_set_populations(evlbm_t h, const void *f, const void *g, int where)
     hipError_t e = hipMemcpyAsync(h->scratch, f, half, k, h->stream);
     if (e == hipSuccess) e = hipMemcpyAsync((char *)h->scratch + half, g, half, k, h->stream);
     if (e != hipSuccess) return hip_fail(e, "copying populations");
-    if (h->refrho)
-        hipLaunchKernelGGL(k_refrho_from_pops, dim3((h->N + 255) / 256), dim3(256), 0, h->stream,
-                           (const double *)h->scratch, h->N, h->Q, h->refrho);
+    if (h->refst) dispatch<RunRefFromPops>(h, (const double *)h->scratch);
     dispatch<RunEncode>(h, (const double *)h->scratch);
     rc = check_launch("k_encode");
     if (rc) return rc;
@@ -776,16 +746,16 @@ int evlbm_checkpoint_save(evlbm_t h, const char *path)
     if (!fp) return fail(EVLBM_EIO, "cannot open %s", path);
     char hdr[512];
     int n = snprintf(hdr, sizeof(hdr),
-                     "{\"format\":\"evlbm-1\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "{\"format\":\"evlbm-2\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%.17g,\"a\":%.17g,\"b\":%.17g,\"kappa\":%.17g,\"tau\":%.17g,\"lambda\":%.17g,"
-                     "\"sphi\":%.17g,\"ref_rho\":%.17g,\"ref_T\":%.17g,\"step\":%lld,\"bytes\":%zu}\n",
+                     "\"sphi\":%.17g,\"step\":%lld,\"bytes\":%zu}\n",
                      h->D, h->nx, h->ny, h->nz, h->storage, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi,
-                     h->ref_rho, h->ref_T, (long long)h->step, bytes);
+                     (long long)h->step, bytes);
     bool ok = fwrite(hdr, 1, n, fp) == (size_t)n && fwrite(host.data(), 1, bytes, fp) == bytes;
-    if (ok && h->refrho) {
-        std::vector<float> r((size_t)h->N);
-        e = hipMemcpy(r.data(), h->refrho, sizeof(float) * h->N, hipMemcpyDeviceToHost);
-        ok = e == hipSuccess && fwrite(r.data(), sizeof(float), h->N, fp) == (size_t)h->N;
+    if (ok && h->refst) {  // the 16-bit reference state, (rho, theta) per cell
+        std::vector<float2> r((size_t)h->N);
+        e = hipMemcpy(r.data(), h->refst, sizeof(float2) * h->N, hipMemcpyDeviceToHost);
+        ok = e == hipSuccess && fwrite(r.data(), sizeof(float2), h->N, fp) == (size_t)h->N;
     }
     ok = (fclose(fp) == 0) && ok;
     if (!ok) return fail(EVLBM_EIO, "writing %s failed", path);
@@ -804,14 +774,14 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
     }
     int D = 0, nx = 0, ny = 0, nz = 0, st = -1;
     long long step = 0;
-    double R, a, b, kappa, tau, lam, sphi, rr, rt;
+    double R, a, b, kappa, tau, lam, sphi;
     size_t bytes = 0;
     int got = sscanf(hdr,
-                     "{\"format\":\"evlbm-1\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "{\"format\":\"evlbm-2\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%lg,\"a\":%lg,\"b\":%lg,\"kappa\":%lg,\"tau\":%lg,\"lambda\":%lg,"
-                     "\"sphi\":%lg,\"ref_rho\":%lg,\"ref_T\":%lg,\"step\":%lld,\"bytes\":%zu}",
-                     &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &rr, &rt, &step, &bytes);
-    if (got != 16) {
+                     "\"sphi\":%lg,\"step\":%lld,\"bytes\":%zu}",
+                     &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &step, &bytes);
+    if (got != 14) {
         fclose(fp);
         return fail(EVLBM_EIO, "bad checkpoint header in %s", path);
     }
@@ -826,15 +796,15 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
     }
     std::vector<char> host(bytes);
     bool ok = fread(host.data(), 1, bytes, fp) == bytes;
-    std::vector<float> r;
-    if (ok && h->refrho) {
+    std::vector<float2> r;
+    if (ok && h->refst) {
         r.resize((size_t)h->N);
-        ok = fread(r.data(), sizeof(float), h->N, fp) == (size_t)h->N;
+        ok = fread(r.data(), sizeof(float2), h->N, fp) == (size_t)h->N;
     }
     fclose(fp);
     if (!ok) return fail(EVLBM_EIO, "truncated checkpoint %s", path);
-    if (h->refrho) {
-        hipError_t e2 = hipMemcpy(h->refrho, r.data(), sizeof(float) * h->N, hipMemcpyHostToDevice);
+    if (h->refst) {
+        hipError_t e2 = hipMemcpy(h->refst, r.data(), sizeof(float2) * h->N, hipMemcpyHostToDevice);
         if (e2 != hipSuccess) return hip_fail(e2, "copying the reference density");
     }
     h->R = R;
@@ -844,8 +814,6 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
     h->tau = tau;
     h->lambda = lam;
     h->sphi = sphi;
-    h->ref_rho = rr;
-    h->ref_T = rt;
     h->cur = 0;
     hipError_t e =
         hipMemcpy2D(h->buf[0], (size_t)h->ds * es, host.data(), row, row, 2 * h->Q, hipMemcpyHostToDevice);

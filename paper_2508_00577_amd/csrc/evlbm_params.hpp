@@ -6,11 +6,9 @@
 
 namespace evlbm {
 
-void reference_populations(int D, double R, double b, double rho, double T, double out[54]);
-
 template <typename R>
-inline StepParams<R> model_params(int D, int storage, double Rg, double a, double b, double kappa, double tau,
-                                  double lambda, double sphi, double ref_rho, double ref_T)
+inline StepParams<R> model_params(double Rg, double a, double b, double kappa, double tau, double lambda,
+                                  double sphi)
 {
     StepParams<R> p;
     p.nx = p.ny = p.nz = 1;
@@ -25,17 +23,7 @@ inline StepParams<R> model_params(int D, int storage, double Rg, double a, doubl
     p.lambda = (R)lambda;
     p.sphi = (R)sphi;
     p.Rgas = (R)Rg;
-    double ref[54];
-    if (storage == EVLBM_F16DEV || storage == EVLBM_BF16DEV) {
-        // per unit density: the equilibrium at rest is proportional to rho at
-        // fixed theta and RT
-        reference_populations(D, Rg, b, ref_rho, ref_T, ref);
-        for (int i = 0; i < 54; ++i) ref[i] /= ref_rho;
-    } else {
-        for (int i = 0; i < 54; ++i) ref[i] = 0.0;
-    }
-    for (int i = 0; i < 54; ++i) p.ref[i] = (R)ref[i];
-    p.refrho = nullptr;
+    p.refst = nullptr;
     return p;
 }
 

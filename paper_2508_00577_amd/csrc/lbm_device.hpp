@@ -52,6 +52,27 @@ __device__ inline uint16_t f32_to_f16_rne(float v)
 
 __device__ inline float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
 
+// Reference of a stored population (16-bit deviation storage): value r and a
+// positive scale s of the population's magnitude; the stored quantity is the
+// scaled deviation (v - r)/s, so its 16 bits resolve the deviation relative
+// to the population itself (FP16 keeps it in its normal range even for the
+// smallest diagonal populations).  Unused ({0, 1}) by the plain storages.
+template <typename R>
+struct Ref {
+    R r, s;
+};
+
+// Reciprocal for the per-cell 1/rho and 1/(1 - b rho): the hardware
+// approximation (<= 1 ulp) in FP32, an exact division in FP64.
+template <typename R>
+__device__ inline R rcp(R x)
+{
+    if constexpr (sizeof(R) == 4)
+        return __builtin_amdgcn_rcpf(x);
+    else
+        return R(1) / x;
+}
+
 // Storage traits: T = stored type, R = arithmetic type.
 template <int S>
 struct Codec;
@@ -60,32 +81,32 @@ template <>
 struct Codec<EVLBM_F64> {
     using T = double;
     using R = double;
-    static __device__ inline R dec(T v, R) { return v; }
-    static __device__ inline T enc(R v, R) { return v; }
+    static __device__ inline R dec(T v, Ref<R>) { return v; }
+    static __device__ inline T enc(R v, Ref<R>) { return v; }
 };
 
 template <>
 struct Codec<EVLBM_F32> {
     using T = float;
     using R = float;
-    static __device__ inline R dec(T v, R) { return v; }
-    static __device__ inline T enc(R v, R) { return v; }
+    static __device__ inline R dec(T v, Ref<R>) { return v; }
+    static __device__ inline T enc(R v, Ref<R>) { return v; }
 };
 
 template <>
 struct Codec<EVLBM_F16DEV> {
     using T = uint16_t;
     using R = float;
-    static __device__ inline R dec(T v, R ref) { return ref + f16_to_f32(v); }
-    static __device__ inline T enc(R v, R ref) { return f32_to_f16_rne(v - ref); }
+    static __device__ inline R dec(T v, Ref<R> q) { return q.r + q.s * f16_to_f32(v); }
+    static __device__ inline T enc(R v, Ref<R> q) { return f32_to_f16_rne((v - q.r) * rcp(q.s)); }
 };
 
 template <>
 struct Codec<EVLBM_BF16DEV> {
     using T = uint16_t;
     using R = float;
-    static __device__ inline R dec(T v, R ref) { return ref + bf16_to_f32(v); }
-    static __device__ inline T enc(R v, R ref) { return f32_to_bf16_rne(v - ref); }
+    static __device__ inline R dec(T v, Ref<R> q) { return q.r + q.s * bf16_to_f32(v); }
+    static __device__ inline T enc(R v, Ref<R> q) { return f32_to_bf16_rne((v - q.r) * rcp(q.s)); }
 };
 
 // ------------------------------------------------------------ parameters
@@ -100,8 +121,7 @@ struct StepParams {
     R wstar;         // (dt/lambda)(1 - beta)
     R lambda, sphi;
     R Rgas;
-    R ref[54];       // deviation storage: reference populations per unit density, f (Q) then g (Q)
-    const float *refrho;  // deviation storage: reference density of every cell (null otherwise)
+    const float2 *refst;  // 16-bit deviation storage: reference state (rho_ref, theta_ref) of every cell
 };
 
 // ------------------------------------------------------------ addressing
@@ -131,16 +151,6 @@ __device__ inline void st_at(T *__restrict__ base, unsigned byte, T v)
         *q = v;
 }
 
-// Reciprocal for the per-cell 1/rho and 1/(1 - b rho): the hardware
-// approximation (<= 1 ulp) in FP32, an exact division in FP64.
-template <typename R>
-__device__ inline R rcp(R x)
-{
-    if constexpr (sizeof(R) == 4)
-        return __builtin_amdgcn_rcpf(x);
-    else
-        return R(1) / x;
-}
 
 // Population access through per-direction pointers: array p (0..2Q-1: f
 // directions, then g) of src or dst at a byte offset.
@@ -242,25 +252,49 @@ __device__ inline PullOffsets pull_offsets(int nx, int ny, int nz, int x, int y,
     return o;
 }
 
-// Reference value of direction i stored at cell s: refrho[s] * W_i for the
-// 16-bit deviation storage, 0 otherwise.
-template <int S, typename R>
-__device__ inline R ref_at(const StepParams<R> &p, int i, long s)
+// Reference of the 16-bit deviation storage: the equilibrium at rest of a
+// per-cell reference state (rho_ref, theta_ref), theta = RT/(1 - b rho).
+// At u = 0 the product equilibrium (eq. feq) is rho prod_a psi(c_a; 0, theta)
+// with psi(0) = 1 - theta and psi(+-1) = theta/2, and the energy equilibrium
+// (eq. geq) is f^eq_i [K + n theta - (D - n) theta^2/(1 - theta)] with
+// K = (3/2) RT and n = |c_i|^2 (O A = 0 and O^2 A = theta^2 at rest: the
+// factors chi(0) = -theta^2 and chi(+-1) = theta^2/2 divided by psi).
+// pop indexes f (0..Q-1) then g (Q..2Q-1).  Scales: f^ref for f, K f^ref for
+// g (both positive).
+template <int D, typename R>
+__device__ inline Ref<R> ref_value(int pop, float2 rs, R b)
+{
+    constexpr int Q = Lat<D>::Q;
+    const int i = pop < Q ? pop : pop - Q;
+    const int n = cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_d<D>(i) * cz_d<D>(i);
+    const R th = (R)rs.y, w0 = R(1) - th, w1 = R(0.5) * th;
+    R f = (R)rs.x;
+#pragma unroll
+    for (int k = 0; k < D; ++k) f *= (k < n) ? w1 : w0;
+    if (pop < Q) return Ref<R>{f, f};
+    const R K = R(1.5) * th * (R(1) - b * (R)rs.x);
+    return Ref<R>{f * (K + R(n) * th - R(D - n) * th * th * rcp(w0)), f * K};
+}
+
+// Reference value of population pop stored at cell s (16-bit storage; 0
+// otherwise).
+template <int D, int S, typename R>
+__device__ inline Ref<R> ref_at(const StepParams<R> &p, int pop, long s)
 {
     if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
-        return (R)p.refrho[s] * p.ref[i];
+        return ref_value<D, R>(pop, p.refst[s], p.b);
     else
-        return R(0);
+        return Ref<R>{R(0), R(1)};
 }
 
 // The same for a cell given by its byte offset in a 16-bit direction array.
-template <int S, typename R>
-__device__ inline R ref_at_b(const StepParams<R> &p, int i, unsigned byte16)
+template <int D, int S, typename R>
+__device__ inline Ref<R> ref_at_b(const StepParams<R> &p, int pop, unsigned byte16)
 {
     if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
-        return (R)ld_at(p.refrho, byte16 * 2u) * p.ref[i];
+        return ref_value<D, R>(pop, ld_at(p.refst, byte16 * 4u), p.b);
     else
-        return R(0);
+        return Ref<R>{R(0), R(1)};
 }
 
 // ---------------------------------------------- per-axis equilibrium factors

@@ -60,8 +60,8 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, c
         const double f = rho * fe[0][kx] * fe[1][ky] * fe[2][kz];
         const double g = rho * ((h * fe[0][kx] + xe[0][kx]) * fe[1][ky] * fe[2][kz] +
                                 fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
-        pop[(long)i * p.ds + cell] = Codec<S>::enc((R)f, ref_at<S>(p, i, cell));
-        pop[(long)(Q + i) * p.ds + cell] = Codec<S>::enc((R)g, ref_at<S>(p, Q + i, cell));
+        pop[(long)i * p.ds + cell] = Codec<S>::enc((R)f, ref_at<D, S>(p, i, cell));
+        pop[(long)(Q + i) * p.ds + cell] = Codec<S>::enc((R)g, ref_at<D, S>(p, Q + i, cell));
     }
 }
 
@@ -80,8 +80,8 @@ __device__ inline void moments_at(const StoreT<S> *__restrict__ pop, RealT<S> *_
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const unsigned s = o.ox[cx_of(i) + 1] + o.oy[cy_of(i) + 1] + o.oz[cz_d<D>(i) + 1];
-        const R f = Codec<S>::dec(ld_at(pop + (long)i * p.ds, s), ref_at_b<S>(p, i, s));
-        const R g = Codec<S>::dec(ld_at(pop + (long)(Q + i) * p.ds, s), ref_at_b<S>(p, Q + i, s));
+        const R f = Codec<S>::dec(ld_at(pop + (long)i * p.ds, s), ref_at_b<D, S>(p, i, s));
+        const R g = Codec<S>::dec(ld_at(pop + (long)(Q + i) * p.ds, s), ref_at_b<D, S>(p, Q + i, s));
         rho += f;
         e += g;
         if (cx_of(i) == 1) jx += f;
@@ -179,16 +179,16 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
     // other directions, so each cell keeps these balances to a single rounding
     // of one stored value and no rounding bias accumulates from step to step.
     constexpr int REST = (Q - 1) / 2;
-    const R fh_rest = Codec<S>::dec(fr[REST], ref_at_b<S>(p, REST, cell));
-    const R gh_rest = Codec<S>::dec(gr[REST], ref_at_b<S>(p, Q + REST, cell));
+    const R fh_rest = Codec<S>::dec(fr[REST], ref_at_b<D, S>(p, REST, cell));
+    const R gh_rest = Codec<S>::dec(gr[REST], ref_at_b<D, S>(p, Q + REST, cell));
     double mass = (double)fh_rest, energy = (double)gh_rest, sf = 0.0, sg = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (i == REST) continue;
         const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
         const unsigned s = o.ox[kx] + o.oy[ky] + o.oz[kz];
-        const R fh = Codec<S>::dec(fr[i], ref_at_b<S>(p, i, s));
-        const R gh = Codec<S>::dec(gr[i], ref_at_b<S>(p, Q + i, s));
+        const R fh = Codec<S>::dec(fr[i], ref_at_b<D, S>(p, i, s));
+        const R gh = Codec<S>::dec(gr[i], ref_at_b<D, S>(p, Q + i, s));
         const R Pyz_e = fe[1][ky] * fe[2][kz];
         const R feq = rho * fe[0][kx] * Pyz_e;
         const R fst = rho * fs[0][kx] * (fs[1][ky] * fs[2][kz]);
@@ -201,7 +201,7 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
         // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq)
         const R fn = omb * fh + c_eq * feq + p.wstar * fst;
         const R gn = omb * gh + c_eq * geq + p.wstar * gst;
-        const R rf = ref_at_b<S>(p, i, cell), rg = ref_at_b<S>(p, Q + i, cell);
+        const Ref<R> rf = ref_at_b<D, S>(p, i, cell), rg = ref_at_b<D, S>(p, Q + i, cell);
         const StoreT<S> fq = Codec<S>::enc(fn, rf);
         const StoreT<S> gq = Codec<S>::enc(gn, rg);
         pops.st(i, cell, fq);
@@ -212,8 +212,8 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
         sg += (double)Codec<S>::dec(gq, rg);
     }
     const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
-    pops.st(REST, cell, Codec<S>::enc((R)(mass - sf), ref_at_b<S>(p, REST, cell)));
-    pops.st(Q + REST, cell, Codec<S>::enc((R)(energy + uF - sg), ref_at_b<S>(p, Q + REST, cell)));
+    pops.st(REST, cell, Codec<S>::enc((R)(mass - sf), ref_at_b<D, S>(p, REST, cell)));
+    pops.st(Q + REST, cell, Codec<S>::enc((R)(energy + uF - sg), ref_at_b<D, S>(p, Q + REST, cell)));
 }
 
 // Pull and collide one cell (x, y, z) from src into dst.
@@ -826,7 +826,7 @@ __global__ void __launch_bounds__(256) k_sums(const StoreT<S> *__restrict__ pop,
         double fmin_ = 1e300;
         for (int i = 0; i < Q; ++i) {
             const long src = (long)xs[cx_of(i) + 1] + (long)p.nx * ((long)ys[cy_of(i) + 1] + (long)p.ny * zs[cz_d<D>(i) + 1]);
-            const double f = Codec<S>::dec(pop[(long)i * p.ds + src], ref_at<S>(p, i, src));
+            const double f = Codec<S>::dec(pop[(long)i * p.ds + src], ref_at<D, S>(p, i, src));
             fmin_ = fmin(fmin_, f);
         }
         v[7] = fmin_;
@@ -882,7 +882,7 @@ __global__ void __launch_bounds__(256) k_scan_nonfinite(const R *__restrict__ m,
 }
 
 // Decode populations to FP64 / encode from FP64 (host I/O, checkpoints).
-template <int S>
+template <int D, int S>
 __global__ void __launch_bounds__(256) k_decode(const StoreT<S> *__restrict__ pop, double *__restrict__ out, long N, int Q2,
                                                 StepParams<RealT<S>> p)
 {
@@ -890,10 +890,10 @@ __global__ void __launch_bounds__(256) k_decode(const StoreT<S> *__restrict__ po
     if (t >= N * Q2) return;
     const int i = (int)(t / N);
     const long c = t - (long)i * N;
-    out[t] = (double)Codec<S>::dec(pop[(long)i * p.ds + c], ref_at<S>(p, i, c));
+    out[t] = (double)Codec<S>::dec(pop[(long)i * p.ds + c], ref_at<D, S>(p, i, c));
 }
 
-template <int S>
+template <int D, int S>
 __global__ void __launch_bounds__(256) k_encode(const double *__restrict__ in, StoreT<S> *__restrict__ pop, long N, int Q2,
                                                 StepParams<RealT<S>> p)
 {
@@ -901,7 +901,7 @@ __global__ void __launch_bounds__(256) k_encode(const double *__restrict__ in, S
     if (t >= N * Q2) return;
     const int i = (int)(t / N);
     const long c = t - (long)i * N;
-    pop[(long)i * p.ds + c] = Codec<S>::enc((RealT<S>)in[t], ref_at<S>(p, i, c));
+    pop[(long)i * p.ds + c] = Codec<S>::enc((RealT<S>)in[t], ref_at<D, S>(p, i, c));
 }
 
 // Validate initial fields: rho > 0, b rho < 1, T > 0 and finite.
@@ -916,14 +916,74 @@ static __global__ void __launch_bounds__(256) k_validate(const double *__restric
 }
 
 // Reference density of every cell = sum of its stored (decoded, FP64) f.
-static __global__ void __launch_bounds__(256) k_refrho_from_pops(const double *__restrict__ f, long N, int Q,
-                                                          float *__restrict__ refrho)
+// 16-bit deviation storage: reference state (rho_ref, theta_ref) of every
+// cell from initial fields (rho, T).
+static __global__ void __launch_bounds__(256) k_ref_from_fields(const double *__restrict__ rho,
+                                                                const double *__restrict__ T, long N, double Rg,
+                                                                double b, float2 *__restrict__ refst)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
-    double s = 0.0;
-    for (int i = 0; i < Q; ++i) s += f[(long)i * N + t];
-    refrho[t] = (float)s;
+    refst[t] = make_float2((float)rho[t], (float)(Rg * T[t] / (1.0 - b * rho[t])));
+}
+
+// The same from populations f, g at rest in the cell's own frame: rho = sum f,
+// j = sum c f, K = sum g/rho - |j|^2/(2 rho^2) = (3/2) RT.
+template <int D>
+__device__ inline float2 ref_state(const double *f, const double *g, double b)
+{
+    constexpr int Q = Lat<D>::Q;
+    double rho = 0.0, e = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < Q; ++i) {
+        rho += f[i];
+        e += g[i];
+        j[0] += cx_of(i) * f[i];
+        j[1] += cy_of(i) * f[i];
+        j[2] += cz_d<D>(i) * f[i];
+    }
+    const double K = e / rho - 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / (rho * rho);
+    return make_float2((float)rho, (float)((2.0 / 3.0) * K / (1.0 - b * rho)));
+}
+
+// From decoded populations in the dense host layout ([Q][N] f, then g).
+template <int D>
+__global__ void __launch_bounds__(256) k_ref_from_pops(const double *__restrict__ pops, long N, double b,
+                                                       float2 *__restrict__ refst)
+{
+    constexpr int Q = Lat<D>::Q;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    double f[Q], g[Q];
+    for (int i = 0; i < Q; ++i) {
+        f[i] = pops[(long)i * N + t];
+        g[i] = pops[(long)(Q + i) * N + t];
+    }
+    refst[t] = ref_state<D>(f, g, b);
+}
+
+// Re-reference in place: decode the 2Q values stored at a cell with its old
+// reference, take the state they carry as the new reference, encode again.
+// Each thread owns one cell (values stored at a cell are encoded with that
+// cell's reference).  p.refst is the old state; refst receives the new one
+// (the same array).
+template <int D, int S>
+__global__ void __launch_bounds__(256) k_rereference(StoreT<S> *__restrict__ pop, float2 *refst,
+                                                     StepParams<RealT<S>> p)
+{
+    constexpr int Q = Lat<D>::Q;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p.N) return;
+    double f[Q], g[Q];
+    for (int i = 0; i < Q; ++i) {
+        f[i] = (double)Codec<S>::dec(pop[(long)i * p.ds + t], ref_at<D, S>(p, i, t));
+        g[i] = (double)Codec<S>::dec(pop[(long)(Q + i) * p.ds + t], ref_at<D, S>(p, Q + i, t));
+    }
+    const float2 rs = ref_state<D>(f, g, (double)p.b);
+    refst[t] = rs;
+    for (int i = 0; i < Q; ++i) {
+        pop[(long)i * p.ds + t] = Codec<S>::enc((RealT<S>)f[i], ref_value<D, RealT<S>>(i, rs, p.b));
+        pop[(long)(Q + i) * p.ds + t] = Codec<S>::enc((RealT<S>)g[i], ref_value<D, RealT<S>>(Q + i, rs, p.b));
+    }
 }
 
 static __global__ void __launch_bounds__(256) k_f64_to_f32(const double *__restrict__ in, float *__restrict__ out, long n)

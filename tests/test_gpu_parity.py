@@ -213,18 +213,16 @@ def test_3d_z_chunks_and_thin_lattices(shape, steps):
 @pytest.mark.parametrize("D,shape,storage", [(2, (1, 40, 96), "f16dev"), (2, (1, 40, 96), "bf16dev"),
                                              (3, (24, 20, 36), "f16dev"), (3, (24, 20, 36), "bf16dev")])
 def test_16bit_deviation_storage_tracks_fp32(D, shape, storage):
-    """Populations stored as 16-bit deviations from a per-cell reference
-    equilibrium, FP32 arithmetic, against the FP32-storage run after 300 steps.
-    FP16 (11-bit significand) meets the 1e-3 density target; BF16 (8-bit)
-    measures ~1e-2 and is held to 3e-2, its stated bound."""
+    """Populations stored as 16-bit deviations from the equilibrium at rest of
+    a per-cell reference state (re-referenced every 100 steps), FP32
+    arithmetic, against the FP32-storage run after 300 steps.  FP16 (11-bit
+    significand) meets the 1e-3 density target; BF16 (8-bit) is held to 3e-2."""
     rho, T = _state("droplet", shape, 0.8, 1e-4)
     nz, ny, nx = shape
     runs = {}
     for st in ("f32", storage):
         L = ev.Lattice(D, nx, ny, nz, storage=st)
         L.set_params(**P)
-        L.set_option(ev.OPT_REF_RHO, float(rho.mean()))
-        L.set_option(ev.OPT_REF_T, float(T.mean()))
         L.init_fields(rho, T)
         L.step(300)
         runs[st] = L.moments()
@@ -254,17 +252,41 @@ def test_checkpoint_resume_is_bitwise(storage, tmp_path):
 
 
 def test_16bit_rereference():
-    """Re-referencing every 100 steps keeps the FP16 run on the FP32 one."""
+    """Re-referencing every 100 steps keeps the FP16 run on the FP32 one, and
+    more closely than the initial reference state kept for the whole run."""
     shape = (1, 40, 96)
     rho, T = _state("droplet", shape, 0.8, 1e-4)
     runs = {}
-    for st, rr in (("f32", 0), ("f16dev", 100)):
+    for key, st, rr in (("f32", "f32", 0), ("kept", "f16dev", 0), ("reref", "f16dev", 100)):
         L = ev.Lattice(2, 96, 40, 1, storage=st)
         L.set_params(**P)
         L.set_option(ev.OPT_REREF_EVERY, rr)
         L.init_fields(rho, T)
-        L.step(300)
-        runs[st] = L.moments()
-    e = _errs(runs["f16dev"], runs["f32"])
-    print(f"f16dev re-referenced: e_rho={e[0]:.2e} e_T={e[2]:.2e}", flush=True)
-    assert e[0] < 1e-3
+        L.step(2000)
+        runs[key] = L.moments()
+    e = _errs(runs["reref"], runs["f32"])
+    e0 = _errs(runs["kept"], runs["f32"])
+    print(f"f16dev 2000 steps: re-referenced e_rho={e[0]:.2e}, kept e_rho={e0[0]:.2e}", flush=True)
+    assert e[0] < 1e-3 and e[0] < e0[0]
+
+
+def test_16bit_long_horizon_3d():
+    """3D droplet (128^3, R = 20, T/Tc = 0.8) after 1e4 steps: FP16 deviation
+    storage (re-referenced every 100 steps) stays within 1e-3 of FP32 storage
+    in density (measured 1.1e-4); BF16 is held to 5e-3 (measured 1.5e-3)."""
+    n = 128
+    shape = (n, n, n)
+    T0 = 0.8 * synth.T_CRIT
+    rl, rv, _ = ev.eos_coexistence(T0, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
+    rho = synth.droplet(shape, 20.0, rl, rv, noise=1e-4)
+    out = {}
+    for st in ("f32", "f16dev", "bf16dev"):
+        L = ev.Lattice(3, n, n, n, storage=st)
+        L.set_params(**P)
+        L.init_fields(rho, np.full(shape, T0))
+        L.step(10000)
+        out[st] = L.moments()[0]
+    for st, bound in (("f16dev", 1e-3), ("bf16dev", 5e-3)):
+        e = np.abs(out[st] - out["f32"]).max() / np.abs(out["f32"]).max()
+        print(f"{st} 128^3 1e4 steps: e_rho {e:.2e}", flush=True)
+        assert e < bound
