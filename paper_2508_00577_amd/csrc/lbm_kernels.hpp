@@ -124,6 +124,25 @@ __device__ inline void pull_pops(const A &pops, const PullOffsets &o, StoreT<S> 
     }
 }
 
+// Store the rest direction r and the opposite pair a, b of a cell so that
+// their three stored values sum to `total` (exact FP64) up to the pair's own
+// rounding: r gets total - na - nb, the pair its updates na, nb plus half of
+// the rest's rounding residual each (b also absorbs a's rounding).
+template <int S, class A>
+__device__ inline void close_three(const A &pops, unsigned cell, int r, int a, int b, double total, RealT<S> na,
+                                   RealT<S> nb, Ref<RealT<S>> qr, Ref<RealT<S>> qa, Ref<RealT<S>> qb)
+{
+    using R = RealT<S>;
+    const StoreT<S> vr = Codec<S>::enc((R)(total - (double)na - (double)nb), qr);
+    const double pair = total - (double)Codec<S>::dec(vr, qr);        // what a + b must carry
+    const double half = 0.5 * (pair - (double)na - (double)nb);      // half the rest's residual
+    const StoreT<S> va = Codec<S>::enc((R)((double)na + half), qa);
+    const StoreT<S> vb = Codec<S>::enc((R)(pair - (double)Codec<S>::dec(va, qa)), qb);
+    pops.st(r, cell, vr);
+    pops.st(a, cell, va);
+    pops.st(b, cell, vb);
+}
+
 // Equilibria (eq. feq, f_star, geq, gstar with eq. g_corr), shifted state
 // (eq. def_ustar with Qtilde = 0) and the update eq. pre_LBM for one cell,
 // from its pulled populations (raw stored values fr, gr of pull_pops) into
@@ -174,14 +193,23 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
 
     // The collision conserves mass and energy exactly: sum f_new = sum fh and
     // sum g_new = sum gh + u.F (eq. pre_LBM with eq. u_shift, T_shift and
-    // Qtilde = 0).  The rest direction is stored last, as the exact (FP64)
-    // incoming sum minus the exact sum of the values actually stored in the
-    // other directions, so each cell keeps these balances to a single rounding
-    // of one stored value and no rounding bias accumulates from step to step.
+    // Qtilde = 0).  Three directions are stored last, after the exact (FP64)
+    // sums of the incoming values and of the values actually stored in the
+    // others: the rest direction takes the remainder less the updates of the
+    // two all-diagonal directions c = +-(1, 1[, 1]), and that pair (the
+    // smallest populations, ~ (theta/2)^D rho) shares what the rounded rest
+    // value leaves, half each, the second member taking the first's rounding
+    // too.  The balance then holds to half an ulp of the pair, and the pair's
+    // opposite velocities keep the residual out of the momentum.  The rest
+    // direction alone is not enough: near a steady state a cell rounds the
+    // same way every step, so its rounding accumulates coherently into a mass
+    // and energy drift.
     constexpr int REST = (Q - 1) / 2;
+    constexpr int SA = Q - 1, SB = 0;  // c = (+1, +1[, +1]) and (-1, -1[, -1])
     const R fh_rest = Codec<S>::dec(fr[REST], ref_at_b<D, S>(p, REST, cell));
     const R gh_rest = Codec<S>::dec(gr[REST], ref_at_b<D, S>(p, Q + REST, cell));
     double mass = (double)fh_rest, energy = (double)gh_rest, sf = 0.0, sg = 0.0;
+    R fn_a = R(0), gn_a = R(0), fn_b = R(0), gn_b = R(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (i == REST) continue;
@@ -201,19 +229,31 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
         // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq)
         const R fn = omb * fh + c_eq * feq + p.wstar * fst;
         const R gn = omb * gh + c_eq * geq + p.wstar * gst;
+        mass += (double)fh;
+        energy += (double)gh;
+        if (i == SA) {
+            fn_a = fn;
+            gn_a = gn;
+            continue;
+        }
+        if (i == SB) {
+            fn_b = fn;
+            gn_b = gn;
+            continue;
+        }
         const Ref<R> rf = ref_at_b<D, S>(p, i, cell), rg = ref_at_b<D, S>(p, Q + i, cell);
         const StoreT<S> fq = Codec<S>::enc(fn, rf);
         const StoreT<S> gq = Codec<S>::enc(gn, rg);
         pops.st(i, cell, fq);
         pops.st(Q + i, cell, gq);
-        mass += (double)fh;
-        energy += (double)gh;
         sf += (double)Codec<S>::dec(fq, rf);
         sg += (double)Codec<S>::dec(gq, rg);
     }
     const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
-    pops.st(REST, cell, Codec<S>::enc((R)(mass - sf), ref_at_b<D, S>(p, REST, cell)));
-    pops.st(Q + REST, cell, Codec<S>::enc((R)(energy + uF - sg), ref_at_b<D, S>(p, Q + REST, cell)));
+    close_three<S>(pops, cell, REST, SA, SB, mass - sf, fn_a, fn_b, ref_at_b<D, S>(p, REST, cell),
+                   ref_at_b<D, S>(p, SA, cell), ref_at_b<D, S>(p, SB, cell));
+    close_three<S>(pops, cell, Q + REST, Q + SA, Q + SB, energy + uF - sg, gn_a, gn_b,
+                   ref_at_b<D, S>(p, Q + REST, cell), ref_at_b<D, S>(p, Q + SA, cell), ref_at_b<D, S>(p, Q + SB, cell));
 }
 
 // Pull and collide one cell (x, y, z) from src into dst.

@@ -140,7 +140,12 @@ def test_global_sums_match_oracle(storage):
     assert sg[4] == pytest.approx(so[4], rel=tol)
     assert sg[5] == pytest.approx(so[5], rel=tol)
     assert sg[6] == pytest.approx(so[6], rel=1e-4 if storage == "f32" else 1e-9)
-    assert sg[7] == pytest.approx(so[7], rel=1e-5 if storage == "f32" else 1e-12)
+    # min f: in FP32 the smallest (all-diagonal) population carries the rest
+    # population's rounding residual, up to half an ulp of an O(1) value
+    if storage == "f32":
+        assert abs(sg[7] - so[7]) < 1.2e-7
+    else:
+        assert sg[7] == pytest.approx(so[7], rel=1e-12)
     assert np.abs(sg[1:4] - so[1:4]).max() < (1e-12 if storage == "f64" else 1e-5) * sg[0]
 
 
@@ -290,3 +295,23 @@ def test_16bit_long_horizon_3d():
         e = np.abs(out[st] - out["f32"]).max() / np.abs(out["f32"]).max()
         print(f"{st} 128^3 1e4 steps: e_rho {e:.2e}", flush=True)
         assert e < bound
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_long_run_mass_is_conserved(storage):
+    """PIN-6 on the GPU over 1e5 steps of a near-steady droplet (96^2): the
+    stored populations keep their total mass.  Near a steady state a cell
+    rounds the same way every step; closing each cell's balance on the rest
+    direction alone let that rounding accumulate (-3.2 of 3882 after 2e5 FP32
+    steps).  The rest direction plus the opposite all-diagonal pair hold it
+    to the pair's rounding (measured 4e-8 after 2e5 steps)."""
+    L = ev.Lattice(2, 96, 96, 1, storage=storage)
+    L.set_params(**P)
+    L.init_droplet(15.0, 0.84)
+    f, _ = L.get_populations()
+    m0 = f.sum()
+    L.step(100000)
+    f, _ = L.get_populations()
+    drift = abs(f.sum() - m0) / m0
+    print(f"{storage}: relative stored-mass drift after 1e5 steps {drift:.2e}", flush=True)
+    assert drift < (1e-9 if storage == "f32" else 1e-6)
