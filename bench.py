@@ -223,6 +223,24 @@ def main():
             extras[f"{st}_rho_rel_err_vs_f32_at_{cmp}_steps"] = err
             del L3
         torch.cuda.empty_cache()
+        # learned warm start (2D 96^2 droplets): train on 12 long runs, then
+        # seed a held-out droplet; distances to the plain run's state after
+        # 1e5 steps, centres of mass aligned
+        from paper_2508_00577_amd import warmstart as W
+        p2 = synth.params()
+        wshape = (1, 96, 96)
+        cases = [(R, Tr) for R in (10.0, 14.0, 18.0, 22.0) for Tr in (0.72, 0.8, 0.88)]
+        t0 = time.perf_counter()
+        X, Y = W.training_samples(cases, wshape, p2, steps=40000, rho_c=1.0)
+        net, hist = W.train_network(X, Y, synth.xavier_params(), iters=3000, lr=2e-3)
+        t_train = time.perf_counter() - t0
+        ws = W.warm_start_study(net, [(15.0, 0.84)], wshape, p2, horizon=100000, check=1000, tol=1e-3)[0]
+        extras["warm_start_96sq_R15_Tr084"] = {
+            "train_s": round(t_train, 2), "train_loss": [float(hist[0]), float(hist[-1])],
+            "steps_to_1e-3_plain": ws["steps_tanh"], "steps_to_1e-3_mlp_matched": ws["steps_mlp_matched"],
+            "err0_plain": ws["err0_tanh"], "err0_mlp_matched": ws["err0_mlp_matched"],
+            "err_1e5_mlp_matched": ws["err_end_mlp_matched"], "err_1e5_mlp_unmatched": ws["err_end_mlp"],
+            "network_used": ws["mlp_used"]}
         result["extras"] = extras
 
     if not args.no_cpu:

@@ -1020,10 +1020,28 @@ __global__ void __launch_bounds__(256) k_rereference(StoreT<S> *__restrict__ pop
     }
     const float2 rs = ref_state<D>(f, g, (double)p.b);
     refst[t] = rs;
+    // re-encode keeping the cell's mass and energy: rest + opposite pair close
+    // the balances as in the collision
+    constexpr int REST = (Q - 1) / 2, SA = Q - 1, SB = 0;
+    using R = RealT<S>;
+    const PtrPops<StoreT<S>> pops{pop, pop, p.ds};
+    const unsigned cb = (unsigned)t * (unsigned)sizeof(StoreT<S>);
+    double mf = 0.0, mg = 0.0, sf = 0.0, sg = 0.0;
     for (int i = 0; i < Q; ++i) {
-        pop[(long)i * p.ds + t] = Codec<S>::enc((RealT<S>)f[i], ref_value<D, RealT<S>>(i, rs, p.b));
-        pop[(long)(Q + i) * p.ds + t] = Codec<S>::enc((RealT<S>)g[i], ref_value<D, RealT<S>>(Q + i, rs, p.b));
+        mf += f[i];
+        mg += g[i];
+        if (i == REST || i == SA || i == SB) continue;
+        const Ref<R> rf = ref_value<D, R>(i, rs, p.b), rg = ref_value<D, R>(Q + i, rs, p.b);
+        const StoreT<S> fq = Codec<S>::enc((R)f[i], rf), gq = Codec<S>::enc((R)g[i], rg);
+        pops.st(i, cb, fq);
+        pops.st(Q + i, cb, gq);
+        sf += (double)Codec<S>::dec(fq, rf);
+        sg += (double)Codec<S>::dec(gq, rg);
     }
+    close_three<S>(pops, cb, REST, SA, SB, mf - sf, (R)f[SA], (R)f[SB], ref_value<D, R>(REST, rs, p.b),
+                   ref_value<D, R>(SA, rs, p.b), ref_value<D, R>(SB, rs, p.b));
+    close_three<S>(pops, cb, Q + REST, Q + SA, Q + SB, mg - sg, (R)g[SA], (R)g[SB], ref_value<D, R>(Q + REST, rs, p.b),
+                   ref_value<D, R>(Q + SA, rs, p.b), ref_value<D, R>(Q + SB, rs, p.b));
 }
 
 static __global__ void __launch_bounds__(256) k_f64_to_f32(const double *__restrict__ in, float *__restrict__ out, long n)
