@@ -493,6 +493,19 @@ __device__ inline R ring_lap(const R *pm, const R *p0, const R *pp, int c, int s
 
 __device__ inline int ring_slot(int k, int n) { return (k + 8 * n) % n; }
 
+// Tile of block b (tiles x fastest, then y, then the z chunk; T tiles per
+// chunk).  Workgroups are dealt round-robin to the 8 XCDs, each with its own
+// L2: XCD j gets the j-th eighth of every chunk, whole rows of tiles, so
+// tiles that share halo lines are resident on the same L2 while all XCDs
+// stream the same chunk (HBM page locality).  Identity when 8 does not
+// divide T; a bijection either way.
+__device__ inline int xcd_tile(int b, int T)
+{
+    if (T & 7) return b;
+    const int per = T >> 3, j = b & 7, k = b >> 3;
+    return (k / per) * T + j * per + k % per;
+}
+
 // BUF selects the population accessor: raw buffer resources (BufPops, valid
 // while 27 N sizeof(T) < 2^32) or per-direction pointers (PtrPops).
 template <int S, int TX, int TY, int ZC, bool BUF>
@@ -515,7 +528,7 @@ __global__ void __launch_bounds__(TX *TY)
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = tx + TX * ty;
-    const int tile = blockIdx.x;  // x fastest, then y, then the z chunk
+    const int tile = xcd_tile(blockIdx.x, nbx * nby);
     const int x0 = (tile % nbx) * TX, y0 = ((tile / nbx) % nby) * TY;
     const int z0 = (tile / (nbx * nby)) * ZC;
     const int z1 = min(z0 + ZC, p.nz);
