@@ -74,3 +74,49 @@ def test_full_size_sampled_step():
     print(f"max relative error: f {ef:.2e}, g {eg:.2e}", flush=True)
     # FP32 arithmetic from identical (FP32-representable) inputs
     assert ef < 1e-5 and eg < 1e-5
+
+
+def test_large_lattice_pointer_path_sampled_step():
+    """A 360^3 FP32 lattice (4.7e7 cells, 20 GB of populations): 27 direction
+    arrays no longer fit one 32-bit buffer range, so the D3Q27 collision takes
+    its per-direction pointer path.  One step after 10 is checked against the
+    oracle on sampled cells, including the lattice's last planes and rows."""
+    n = 360
+    params = synth.params()
+    T0 = 0.8 * synth.T_CRIT
+    rl, rv, _ = ev.eos_coexistence(T0, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
+    shape = (n, n, n)
+    rho = synth.droplet(shape, 56.0, rl, rv, noise=1e-4, seed=synth.SEED + 2)
+    L = ev.Lattice(3, n, n, n, storage="f32")
+    L.set_params(**params)
+    L.init_fields(rho, np.full(shape, T0))
+    del rho
+    L.step(10)
+    c = n // 2
+    cells = [(0, 0, 0), (n - 1, n - 1, n - 1), (n - 1, 0, n - 1), (c + 56, c, c), (c, c - 56, c), (319, 359, 351),
+             (320, 356, 352), (63, 3, 31), (c, c, c), (200, 5, 355)]
+    f0, g0 = L.get_populations(device=True)
+    idx = torch.arange(-4, 5, device=f0.device)
+    windows = []
+    for (x, y, z) in cells:
+        xs, ys, zs = (idx + x) % n, (idx + y) % n, (idx + z) % n
+        windows.append((f0[:, zs][:, :, ys][:, :, :, xs].cpu().numpy(), g0[:, zs][:, :, ys][:, :, :, xs].cpu().numpy()))
+    del f0, g0
+    torch.cuda.empty_cache()
+    L.step(1)
+    f1, g1 = L.get_populations(device=True)
+    cx = torch.tensor([p[0] for p in cells], device=f1.device)
+    cy = torch.tensor([p[1] for p in cells], device=f1.device)
+    cz = torch.tensor([p[2] for p in cells], device=f1.device)
+    gf = f1[:, cz, cy, cx].T.cpu().numpy()
+    gg = g1[:, cz, cy, cx].T.cpu().numpy()
+    del f1, g1
+    torch.cuda.empty_cache()
+    of = np.empty_like(gf)
+    og = np.empty_like(gg)
+    for k, (wf, wg) in enumerate(windows):
+        of[k], og[k] = oracle.step_window(3, wf, wg, params)
+    ef = np.abs(gf - of).max() / np.abs(of).max()
+    eg = np.abs(gg - og).max() / np.abs(og).max()
+    print(f"360^3 f32 pointer path: max relative error f {ef:.2e}, g {eg:.2e}", flush=True)
+    assert ef < 1e-5 and eg < 1e-5
