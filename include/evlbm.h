@@ -189,7 +189,7 @@ int evlbm_batch_set_params(evlbm_batch_t b, double R, double a, double bexcl, do
 
 /* Initialise domain k from host FP64 fields rho[N_k], u[2 N_k] (nullable), T[N_k].
  * With 16-bit storage the domain's per-cell reference state is taken from
- * these fields and kept (batched domains are not re-referenced).
+ * these fields and refreshed every 100 steps of the batch, as on a lattice.
  * Errors: EINVAL, ENONPHYS, ENONFINITE. */
 int evlbm_batch_init_domain(evlbm_batch_t b, int k, const double *rho, const double *u, const double *T);
 

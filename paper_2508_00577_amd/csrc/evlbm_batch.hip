@@ -97,6 +97,7 @@ struct evlbm_batch {
     double R = 1.0, a = 0.0, b = 0.0, kappa = 0.0, tau = 1.0, lambda = 1.0, sphi = -1.0;
     int cur = 0;
     int64_t step = 0;
+    int64_t reref_every = 100;  // 16-bit storage: re-reference period in steps (as a lattice's default)
     bool m_valid = false;
     std::vector<char> initialized;
     hipGraphExec_t graph_exec_par[2] = {nullptr, nullptr};
@@ -201,6 +202,16 @@ struct BDispatchS {
         BOps<S, 1>::occupancy(b, cus);
         BOps<S, 2>::occupancy(b, cus);
         BOps<S, 3>::occupancy(b, cus);
+    }
+    // 16-bit storage: re-reference domain k in place (as on a lattice)
+    static void rereference(evlbm_batch *b, int k)
+    {
+        if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV) {
+            const DomainRec &d = b->doms[k];
+            hipLaunchKernelGGL((k_rereference<2, S>), dim3((d.N + 255) / 256), dim3(256), 0, b->stream,
+                               (StoreT<S> *)b->buf[b->cur] + d.pop_off, b->refst + d.cell_off,
+                               dparams<RealT<S>>(b, k));
+        }
     }
     // single-domain helpers (initialisation, readout, population I/O)
     static void init(evlbm_batch *b, int k, const double *rho, const double *u, const double *T0)
@@ -415,8 +426,20 @@ int evlbm_batch_step(evlbm_batch_t b, int64_t nsteps)
     for (int k = 0; k < b->n; ++k)
         if (!b->initialized[k]) return fail(EVLBM_ESTATE, "domain %d not initialised", k);
     if (nsteps < 0) return fail(EVLBM_EINVAL, "nsteps must be >= 0");
-    int rc = brun(b, nsteps, true);
-    if (rc) return rc;
+    const bool dev16 = b->storage == EVLBM_F16DEV || b->storage == EVLBM_BF16DEV;
+    const int64_t reref = dev16 ? b->reref_every : 0;
+    int64_t done = 0;
+    while (done < nsteps) {
+        int64_t chunk = nsteps - done;
+        if (reref > 0) chunk = std::min<int64_t>(chunk, reref - (b->step % reref));
+        int rc = brun(b, chunk, true);
+        if (rc) return rc;
+        done += chunk;
+        if (reref > 0 && b->step % reref == 0) {
+            for (int k = 0; k < b->n; ++k) BATCH_DISPATCH(rereference(b, k));
+            b->m_valid = false;
+        }
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batch step");
     return EVLBM_OK;

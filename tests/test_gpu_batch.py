@@ -37,17 +37,18 @@ def _batch(storage, variant=0):
     return b, fields
 
 
-@pytest.mark.parametrize("storage", ["f32", "f64"])
-def test_batch_domain_equals_single_lattice_bitwise(storage):
+@pytest.mark.parametrize("storage,steps", [("f32", 70), ("f64", 70), ("f16dev", 230)])
+def test_batch_domain_equals_single_lattice_bitwise(storage, steps):
     """PIN-18: with the same tile shape (64 x 4) a batched domain evolves bit for
-    bit as the same domain stepped alone."""
+    bit as the same domain stepped alone (16-bit storage: across two
+    re-references, at steps 100 and 200)."""
     b, fields = _batch(storage, 0)
-    b.step(70)
+    b.step(steps)
     for k, (kind, nx, ny, Tr) in enumerate(DOMS):
         L = ev.Lattice(2, nx, ny, 1, storage=storage)
         L.set_params(**P)
         L.init_fields(*fields[k])
-        L.step(70)
+        L.step(steps)
         fa, ga = b.get_populations(k)
         fb, gb = L.get_populations()
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb), f"domain {k}"
