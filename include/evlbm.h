@@ -70,12 +70,14 @@ typedef struct evlbm_lattice *evlbm_t;
 /* Message of the last failed call on this thread (never NULL). */
 const char *evlbm_last_error(void);
 
-/* Create a periodic lattice of nx*ny*nz cells (D2Q9 needs nz == 1) with the
- * given storage, bound to `stream` (a hipStream_t; NULL = default stream) on
- * the current device.  Allocates two population buffers (2*2Q*N values) and a
- * moment field.  Parameters start at R = 1, a = b = kappa = 0, tau = lambda = 1.
+/* Create a periodic lattice of N = nx*ny*nz cells (D2Q9 needs nz == 1) with
+ * the given storage, bound to `stream` (a hipStream_t; NULL = default stream)
+ * on the current device.  Allocates two population buffers of 2Q direction
+ * arrays each (N values, consecutive arrays 1280 bytes apart beyond their
+ * size), a moment field and, for 16-bit storage, the per-cell reference
+ * state.  Parameters start at R = 1, a = b = kappa = 0, tau = lambda = 1.
  * Errors: EINVAL (unknown lattice or storage, sizes <= 0, nz != 1 for D2Q9,
- * nx*ny*nz*8 >= 2^32 for FP64 storage or nx*ny*nz*4 >= 2^32 otherwise: the
+ * N*8 + 1280 >= 2^32 for FP64 storage or N*4 + 1280 >= 2^32 otherwise: the
  * kernels address each per-direction array with 32-bit byte offsets),
  * ENOMEM, EHIP. */
 int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream, evlbm_t *out);
@@ -99,6 +101,7 @@ int evlbm_set_option(evlbm_t h, int key, double value);
 
 /* Initialise f = f^eq(rho, u, P0/rho) and g = g^eq(u, RT) cell by cell from
  * rho[N], u[D*N] (may be NULL: at rest) and T[N]; resets the step count.
+ * With 16-bit storage the per-cell reference state is taken from rho and T.
  * Errors: EINVAL (bad where), ENONPHYS (rho <= 0, b rho >= 1 or T <= 0),
  * ENONFINITE, EHIP. */
 int evlbm_init_fields(evlbm_t h, const void *rho, const void *u, const void *T, int where);
@@ -133,13 +136,19 @@ int evlbm_global_sums(evlbm_t h, double out[8]);
 int evlbm_measure(evlbm_t h, int kind, const double *geom, double out[8]);
 
 /* Copy the stored populations out (decoded) or in (encoded): f[Q*N], g[Q*N]
- * in the library layout.  Errors: EINVAL, EHIP. */
+ * dense, [Q][nz][ny][nx] each, FP64 on the host (HOST_F64) or the device
+ * (DEVICE_F64).  With 16-bit storage, set_populations also takes the per-cell
+ * reference state from the values it is given.  Blocks.  Errors: EINVAL (null
+ * pointer, other `where`), ENOMEM, EHIP. */
 int evlbm_get_populations(evlbm_t h, void *f, void *g, int where);
 int evlbm_set_populations(evlbm_t h, const void *f, const void *g, int where);
 
-/* Bit-exact dump of the stored populations with a text header (lattice,
- * storage, sizes, parameters, step); load restores them into a handle of
- * the same lattice, sizes and storage.  Errors: EIO, EINVAL. */
+/* Bit-exact dump of the stored populations, dense [2Q][N], after a one-line
+ * JSON header (format evlbm-2: lattice, storage, sizes, parameters, step,
+ * byte count), followed for 16-bit storage by the per-cell reference state
+ * (rho_ref, theta_ref) as FP32 pairs.  Load restores all of it into a handle
+ * of the same lattice, sizes and storage.  Errors: EIO (open, read, write,
+ * bad header, wrong byte count), EINVAL (null argument, different lattice). */
 int evlbm_checkpoint_save(evlbm_t h, const char *path);
 int evlbm_checkpoint_load(evlbm_t h, const char *path);
 
