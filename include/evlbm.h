@@ -144,9 +144,9 @@ int evlbm_get_populations(evlbm_t h, void *f, void *g, int where);
 int evlbm_set_populations(evlbm_t h, const void *f, const void *g, int where);
 
 /* Bit-exact dump of the stored populations, dense [2Q][N], after a one-line
- * JSON header (format evlbm-2: lattice, storage, sizes, parameters, step,
+ * JSON header (format evlbm-3: lattice, storage, sizes, parameters, step,
  * byte count), followed for 16-bit storage by the per-cell reference state
- * (rho_ref, theta_ref) as FP32 pairs.  Load restores all of it into a handle
+ * as four FP32 values per cell.  Load restores all of it into a handle
  * of the same lattice, sizes and storage.  Errors: EIO (open, read, write,
  * bad header, wrong byte count), EINVAL (null argument, different lattice). */
 int evlbm_checkpoint_save(evlbm_t h, const char *path);

@@ -86,7 +86,7 @@ struct evlbm_batch {
     void *buf[2] = {nullptr, nullptr};
     void *m = nullptr;
     void *lap = nullptr;
-    float2 *refst = nullptr;  // 16-bit storage: reference (rho, theta) per cell of every domain
+    float4 *refst = nullptr;  // 16-bit storage: reference state per cell of every domain
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     DomainRec *d_dom = nullptr;
@@ -350,7 +350,7 @@ int evlbm_batch_create(int n, const evlbm_domain_desc *d, int storage, void *str
     if (e == hipSuccess) e = hipMalloc(&b->m, (size_t)mo * rbytes(storage));
     if (e == hipSuccess) e = hipMalloc(&b->lap, (size_t)cells * rbytes(storage));
     if (e == hipSuccess && (storage == EVLBM_F16DEV || storage == EVLBM_BF16DEV))
-        e = hipMalloc(&b->refst, (size_t)cells * sizeof(float2));
+        e = hipMalloc(&b->refst, (size_t)cells * sizeof(float4));
     if (e == hipSuccess) e = hipMalloc(&b->d_dom, sizeof(DomainRec) * n);
     if (e == hipSuccess) e = hipMemcpy(b->d_dom, b->doms.data(), sizeof(DomainRec) * n, hipMemcpyHostToDevice);
     // tile lists per compiled shape, domain by domain, row-major tiles
@@ -409,7 +409,7 @@ int evlbm_batch_init_domain(evlbm_batch_t b, int k, const double *rho, const dou
     if (e == hipSuccess && u) e = hipMemcpyAsync(du, u, sizeof(double) * 2 * d.N, hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return hip_fail(e, "copying initial fields");
     if (b->refst)
-        hipLaunchKernelGGL(k_ref_from_fields, dim3((d.N + 255) / 256), dim3(256), 0, b->stream, (const double *)dr,
+        hipLaunchKernelGGL(k_ref_from_fields<2>, dim3((d.N + 255) / 256), dim3(256), 0, b->stream, (const double *)dr,
                            (const double *)dt, d.N, b->R, b->b, b->refst + d.cell_off);
     BATCH_DISPATCH(init(b, k, dr, du, dt));
     e = hipStreamSynchronize(b->stream);

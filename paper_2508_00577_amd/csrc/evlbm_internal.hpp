@@ -16,7 +16,7 @@ struct evlbm_lattice {
     int cur = 0;                        // buffer holding the current state
     void *m = nullptr;                  // pulled moments rho, j (D), e: [(D+2)][N]
     void *lap = nullptr;                // readout scratch: lap rho [N]
-    float2 *refst = nullptr;            // 16-bit deviation storage: reference (rho, theta) per cell [N]
+    float4 *refst = nullptr;            // 16-bit deviation storage: reference state per cell [N]
     void *scratch = nullptr;            // I/O and reduction scratch
     size_t scratch_bytes = 0;
     // model

@@ -419,7 +419,7 @@ int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream,
     e = hipMalloc(&h->m, m_bytes);
     if (e == hipSuccess) e = hipMalloc(&h->lap, (size_t)h->N * real_bytes(storage));
     if (e == hipSuccess && (storage == EVLBM_F16DEV || storage == EVLBM_BF16DEV))
-        e = hipMalloc(&h->refst, (size_t)h->N * sizeof(float2));
+        e = hipMalloc(&h->refst, (size_t)h->N * sizeof(float4));
     if (e != hipSuccess) {
         evlbm_destroy(h);
         return fail(EVLBM_ENOMEM, "hipMalloc for moment fields: %s", hipGetErrorString(e));
@@ -554,9 +554,14 @@ int evlbm_init_fields(evlbm_t h, const void *rho, const void *u, const void *T, 
         if (host & 1) return fail(EVLBM_ENONPHYS, "need rho > 0, b rho < 1, T > 0 everywhere");
     }
     h->cur = 0;
-    if (h->refst)
-        hipLaunchKernelGGL(k_ref_from_fields, dim3((N + 255) / 256), dim3(256), 0, h->stream, (const double *)d_rho,
-                           (const double *)d_T, N, h->R, h->b, h->refst);
+    if (h->refst) {
+        if (h->D == 2)
+            hipLaunchKernelGGL(k_ref_from_fields<2>, dim3((N + 255) / 256), dim3(256), 0, h->stream,
+                               (const double *)d_rho, (const double *)d_T, N, h->R, h->b, h->refst);
+        else
+            hipLaunchKernelGGL(k_ref_from_fields<3>, dim3((N + 255) / 256), dim3(256), 0, h->stream,
+                               (const double *)d_rho, (const double *)d_T, N, h->R, h->b, h->refst);
+    }
     dispatch<RunInit>(h, (const double *)d_rho, (const double *)d_u, (const double *)d_T);
     rc = check_launch("k_init");
     if (rc) return rc;
@@ -746,16 +751,16 @@ int evlbm_checkpoint_save(evlbm_t h, const char *path)
     if (!fp) return fail(EVLBM_EIO, "cannot open %s", path);
     char hdr[512];
     int n = snprintf(hdr, sizeof(hdr),
-                     "{\"format\":\"evlbm-2\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "{\"format\":\"evlbm-3\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%.17g,\"a\":%.17g,\"b\":%.17g,\"kappa\":%.17g,\"tau\":%.17g,\"lambda\":%.17g,"
                      "\"sphi\":%.17g,\"step\":%lld,\"bytes\":%zu}\n",
                      h->D, h->nx, h->ny, h->nz, h->storage, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi,
                      (long long)h->step, bytes);
     bool ok = fwrite(hdr, 1, n, fp) == (size_t)n && fwrite(host.data(), 1, bytes, fp) == bytes;
-    if (ok && h->refst) {  // the 16-bit reference state, (rho, theta) per cell
-        std::vector<float2> r((size_t)h->N);
-        e = hipMemcpy(r.data(), h->refst, sizeof(float2) * h->N, hipMemcpyDeviceToHost);
-        ok = e == hipSuccess && fwrite(r.data(), sizeof(float2), h->N, fp) == (size_t)h->N;
+    if (ok && h->refst) {  // the 16-bit reference state of every cell
+        std::vector<float4> r((size_t)h->N);
+        e = hipMemcpy(r.data(), h->refst, sizeof(float4) * h->N, hipMemcpyDeviceToHost);
+        ok = e == hipSuccess && fwrite(r.data(), sizeof(float4), h->N, fp) == (size_t)h->N;
     }
     ok = (fclose(fp) == 0) && ok;
     if (!ok) return fail(EVLBM_EIO, "writing %s failed", path);
@@ -777,7 +782,7 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
     double R, a, b, kappa, tau, lam, sphi;
     size_t bytes = 0;
     int got = sscanf(hdr,
-                     "{\"format\":\"evlbm-2\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "{\"format\":\"evlbm-3\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%lg,\"a\":%lg,\"b\":%lg,\"kappa\":%lg,\"tau\":%lg,\"lambda\":%lg,"
                      "\"sphi\":%lg,\"step\":%lld,\"bytes\":%zu}",
                      &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &step, &bytes);
@@ -796,15 +801,15 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
     }
     std::vector<char> host(bytes);
     bool ok = fread(host.data(), 1, bytes, fp) == bytes;
-    std::vector<float2> r;
+    std::vector<float4> r;
     if (ok && h->refst) {
         r.resize((size_t)h->N);
-        ok = fread(r.data(), sizeof(float2), h->N, fp) == (size_t)h->N;
+        ok = fread(r.data(), sizeof(float4), h->N, fp) == (size_t)h->N;
     }
     fclose(fp);
     if (!ok) return fail(EVLBM_EIO, "truncated checkpoint %s", path);
     if (h->refst) {
-        hipError_t e2 = hipMemcpy(h->refst, r.data(), sizeof(float2) * h->N, hipMemcpyHostToDevice);
+        hipError_t e2 = hipMemcpy(h->refst, r.data(), sizeof(float4) * h->N, hipMemcpyHostToDevice);
         if (e2 != hipSuccess) return hip_fail(e2, "copying the reference density");
     }
     h->R = R;

@@ -52,14 +52,16 @@ __device__ inline uint16_t f32_to_f16_rne(float v)
 
 __device__ inline float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
 
-// Reference of a stored population (16-bit deviation storage): value r and a
-// positive scale s of the population's magnitude; the stored quantity is the
-// scaled deviation (v - r)/s, so its 16 bits resolve the deviation relative
-// to the population itself (FP16 keeps it in its normal range even for the
-// smallest diagonal populations).  Unused ({0, 1}) by the plain storages.
+// Reference of a stored population (16-bit deviation storage): value r, a
+// positive scale s of the population's magnitude and, where the population
+// is encoded, is ~ 1/s; the stored quantity is the scaled deviation
+// (v - r) is, decoded as r + s h, so its 16 bits resolve the deviation
+// relative to the population itself (FP16 keeps it in its normal range even
+// for the smallest diagonal populations).  Unused ({0, 1, 1}) by the plain
+// storages.
 template <typename R>
 struct Ref {
-    R r, s;
+    R r, s, is;
 };
 
 // Reciprocal for the per-cell 1/rho and 1/(1 - b rho): the hardware
@@ -98,7 +100,7 @@ struct Codec<EVLBM_F16DEV> {
     using T = uint16_t;
     using R = float;
     static __device__ inline R dec(T v, Ref<R> q) { return q.r + q.s * f16_to_f32(v); }
-    static __device__ inline T enc(R v, Ref<R> q) { return f32_to_f16_rne((v - q.r) * rcp(q.s)); }
+    static __device__ inline T enc(R v, Ref<R> q) { return f32_to_f16_rne((v - q.r) * q.is); }
 };
 
 template <>
@@ -106,7 +108,7 @@ struct Codec<EVLBM_BF16DEV> {
     using T = uint16_t;
     using R = float;
     static __device__ inline R dec(T v, Ref<R> q) { return q.r + q.s * bf16_to_f32(v); }
-    static __device__ inline T enc(R v, Ref<R> q) { return f32_to_bf16_rne((v - q.r) * rcp(q.s)); }
+    static __device__ inline T enc(R v, Ref<R> q) { return f32_to_bf16_rne((v - q.r) * q.is); }
 };
 
 // ------------------------------------------------------------ parameters
@@ -121,7 +123,7 @@ struct StepParams {
     R wstar;         // (dt/lambda)(1 - beta)
     R lambda, sphi;
     R Rgas;
-    const float2 *refst;  // 16-bit deviation storage: reference state (rho_ref, theta_ref) of every cell
+    const float4 *refst;  // 16-bit deviation storage: reference state of every cell (ref_state_of)
 };
 
 // ------------------------------------------------------------ addressing
@@ -253,48 +255,122 @@ __device__ inline PullOffsets pull_offsets(int nx, int ny, int nz, int x, int y,
 }
 
 // Reference of the 16-bit deviation storage: the equilibrium at rest of a
-// per-cell reference state (rho_ref, theta_ref), theta = RT/(1 - b rho).
-// At u = 0 the product equilibrium (eq. feq) is rho prod_a psi(c_a; 0, theta)
-// with psi(0) = 1 - theta and psi(+-1) = theta/2, and the energy equilibrium
-// (eq. geq) is f^eq_i [K + n theta - (D - n) theta^2/(1 - theta)] with
-// K = (3/2) RT and n = |c_i|^2 (O A = 0 and O^2 A = theta^2 at rest: the
-// factors chi(0) = -theta^2 and chi(+-1) = theta^2/2 divided by psi).
-// pop indexes f (0..Q-1) then g (Q..2Q-1).  Scales: f^ref for f, K f^ref for
-// g (both positive).
+// per-cell reference state (rho, theta = RT/(1 - b rho), K = (3/2) RT).  At
+// u = 0 the product equilibrium (eq. feq) is rho prod_a psi(c_a; 0, theta)
+// with psi(0) = w0 = 1 - theta and psi(+-1) = w1 = theta/2, so for
+// n = |c_i|^2 it is a0 q^n with a0 = rho w0^D and q = w1/w0; the energy
+// equilibrium (eq. geq) is f^eq_i [K + n theta - (D - n) theta^2/(1 - theta)]
+// = f^eq_i (A + n B) with A = K - D theta^2/(1 - theta) and B =
+// theta/(1 - theta) (O A = 0 and O^2 A = theta^2 at rest: the factors
+// chi(0) = -theta^2 and chi(+-1) = theta^2/2 divided by psi).  A cell stores
+// the state as {a0, q, A, B}; scales are f^eq for f and B f^eq for g (both
+// positive).
+template <int D>
+__host__ __device__ inline float4 ref_state_of(double rho, double theta, double K)
+{
+    const double w0 = 1.0 - theta, w1 = 0.5 * theta;
+    double a0 = rho;
+    for (int k = 0; k < D; ++k) a0 *= w0;
+    return make_float4((float)a0, (float)(w1 / w0), (float)(K - D * theta * theta / w0), (float)(theta / w0));
+}
+
+// Reference value and scale of population pop (f 0..Q-1, then g) for a cell
+// with reference state rs (decode side: is left 0).
 template <int D, typename R>
-__device__ inline Ref<R> ref_value(int pop, float2 rs, R b)
+__device__ inline Ref<R> ref_value(int pop, float4 rs)
 {
     constexpr int Q = Lat<D>::Q;
     const int i = pop < Q ? pop : pop - Q;
     const int n = cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_d<D>(i) * cz_d<D>(i);
-    const R th = (R)rs.y, w0 = R(1) - th, w1 = R(0.5) * th;
     R f = (R)rs.x;
-#pragma unroll
-    for (int k = 0; k < D; ++k) f *= (k < n) ? w1 : w0;
-    if (pop < Q) return Ref<R>{f, f};
-    const R K = R(1.5) * th * (R(1) - b * (R)rs.x);
-    return Ref<R>{f * (K + R(n) * th - R(D - n) * th * th * rcp(w0)), f * K};
+    for (int k = 0; k < n; ++k) f *= (R)rs.y;
+    if (pop < Q) return Ref<R>{f, f, R(0)};
+    return Ref<R>{f * ((R)rs.z + R(n) * (R)rs.w), f * (R)rs.w, R(0)};
 }
 
-// Reference value of population pop stored at cell s (16-bit storage; 0
-// otherwise).
+// The reciprocals an encoding cell needs, computed once per cell.
+template <typename R>
+struct RefInv {
+    R ia0, iq, iB;
+};
+
+template <typename R>
+__device__ inline RefInv<R> ref_inv(float4 rs)
+{
+    return RefInv<R>{rcp((R)rs.x), rcp((R)rs.y), rcp((R)rs.w)};
+}
+
+// Encode side: the reference with is = 1/s from the cell's reciprocals.
+template <int D, typename R>
+__device__ inline Ref<R> ref_value_enc(int pop, float4 rs, RefInv<R> v)
+{
+    constexpr int Q = Lat<D>::Q;
+    Ref<R> q = ref_value<D, R>(pop, rs);
+    const int i = pop < Q ? pop : pop - Q;
+    const int n = cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_d<D>(i) * cz_d<D>(i);
+    R is = v.ia0;
+    for (int k = 0; k < n; ++k) is *= v.iq;
+    q.is = pop < Q ? is : is * v.iB;
+    return q;
+}
+
+// Reference state of the cell at element index s / 16-bit byte offset byte16.
+template <int S, typename R>
+__device__ inline float4 ref_state_at(const StepParams<R> &p, long s)
+{
+    if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
+        return p.refst[s];
+    else
+        return make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+template <int S, typename R>
+__device__ inline float4 ref_state_at_b(const StepParams<R> &p, unsigned byte16)
+{
+    if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
+        return ld_at(p.refst, byte16 * 8u);
+    else
+        return make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Decode-side reference of population pop stored at cell s (element index)
+// or at 16-bit byte offset byte16; {0, 1, 1} for the plain storages.
 template <int D, int S, typename R>
 __device__ inline Ref<R> ref_at(const StepParams<R> &p, int pop, long s)
 {
     if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
-        return ref_value<D, R>(pop, p.refst[s], p.b);
+        return ref_value<D, R>(pop, p.refst[s]);
     else
-        return Ref<R>{R(0), R(1)};
+        return Ref<R>{R(0), R(1), R(1)};
 }
 
-// The same for a cell given by its byte offset in a 16-bit direction array.
 template <int D, int S, typename R>
 __device__ inline Ref<R> ref_at_b(const StepParams<R> &p, int pop, unsigned byte16)
 {
     if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
-        return ref_value<D, R>(pop, ld_at(p.refst, byte16 * 4u), p.b);
+        return ref_value<D, R>(pop, ld_at(p.refst, byte16 * 8u));
     else
-        return Ref<R>{R(0), R(1)};
+        return Ref<R>{R(0), R(1), R(1)};
+}
+
+// Encode-side reference of population pop of a cell whose state rs and
+// reciprocals inv were loaded once.
+template <int D, int S, typename R>
+__device__ inline Ref<R> ref_enc(int pop, float4 rs, RefInv<R> inv)
+{
+    if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
+        return ref_value_enc<D, R>(pop, rs, inv);
+    else
+        return Ref<R>{R(0), R(1), R(1)};
+}
+
+template <int S, typename R>
+__device__ inline RefInv<R> ref_inv_of(float4 rs)
+{
+    if constexpr (S == EVLBM_F16DEV || S == EVLBM_BF16DEV)
+        return ref_inv<R>(rs);
+    else
+        return RefInv<R>{R(1), R(1), R(1)};
 }
 
 // ---------------------------------------------- per-axis equilibrium factors

@@ -54,14 +54,16 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, c
         }
     }
     const double h = 1.5 * RT;
+    const float4 rs = ref_state_at<S>(p, cell);
+    const RefInv<R> inv = ref_inv_of<S, R>(rs);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
         const double f = rho * fe[0][kx] * fe[1][ky] * fe[2][kz];
         const double g = rho * ((h * fe[0][kx] + xe[0][kx]) * fe[1][ky] * fe[2][kz] +
                                 fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
-        pop[(long)i * p.ds + cell] = Codec<S>::enc((R)f, ref_at<D, S>(p, i, cell));
-        pop[(long)(Q + i) * p.ds + cell] = Codec<S>::enc((R)g, ref_at<D, S>(p, Q + i, cell));
+        pop[(long)i * p.ds + cell] = Codec<S>::enc((R)f, ref_enc<D, S>(i, rs, inv));
+        pop[(long)(Q + i) * p.ds + cell] = Codec<S>::enc((R)g, ref_enc<D, S>(Q + i, rs, inv));
     }
 }
 
@@ -206,8 +208,10 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
     // and energy drift.
     constexpr int REST = (Q - 1) / 2;
     constexpr int SA = Q - 1, SB = 0;  // c = (+1, +1[, +1]) and (-1, -1[, -1])
-    const R fh_rest = Codec<S>::dec(fr[REST], ref_at_b<D, S>(p, REST, cell));
-    const R gh_rest = Codec<S>::dec(gr[REST], ref_at_b<D, S>(p, Q + REST, cell));
+    const float4 rsc = ref_state_at_b<S>(p, cell);  // the cell's own reference state
+    const RefInv<R> invc = ref_inv_of<S, R>(rsc);
+    const R fh_rest = Codec<S>::dec(fr[REST], ref_enc<D, S>(REST, rsc, invc));
+    const R gh_rest = Codec<S>::dec(gr[REST], ref_enc<D, S>(Q + REST, rsc, invc));
     double mass = (double)fh_rest, energy = (double)gh_rest, sf = 0.0, sg = 0.0;
     R fn_a = R(0), gn_a = R(0), fn_b = R(0), gn_b = R(0);
 #pragma unroll
@@ -241,7 +245,7 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
             gn_b = gn;
             continue;
         }
-        const Ref<R> rf = ref_at_b<D, S>(p, i, cell), rg = ref_at_b<D, S>(p, Q + i, cell);
+        const Ref<R> rf = ref_enc<D, S>(i, rsc, invc), rg = ref_enc<D, S>(Q + i, rsc, invc);
         const StoreT<S> fq = Codec<S>::enc(fn, rf);
         const StoreT<S> gq = Codec<S>::enc(gn, rg);
         pops.st(i, cell, fq);
@@ -250,10 +254,11 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
         sg += (double)Codec<S>::dec(gq, rg);
     }
     const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
-    close_three<S>(pops, cell, REST, SA, SB, mass - sf, fn_a, fn_b, ref_at_b<D, S>(p, REST, cell),
-                   ref_at_b<D, S>(p, SA, cell), ref_at_b<D, S>(p, SB, cell));
+    close_three<S>(pops, cell, REST, SA, SB, mass - sf, fn_a, fn_b, ref_enc<D, S>(REST, rsc, invc),
+                   ref_enc<D, S>(SA, rsc, invc), ref_enc<D, S>(SB, rsc, invc));
     close_three<S>(pops, cell, Q + REST, Q + SA, Q + SB, energy + uF - sg, gn_a, gn_b,
-                   ref_at_b<D, S>(p, Q + REST, cell), ref_at_b<D, S>(p, Q + SA, cell), ref_at_b<D, S>(p, Q + SB, cell));
+                   ref_enc<D, S>(Q + REST, rsc, invc), ref_enc<D, S>(Q + SA, rsc, invc),
+                   ref_enc<D, S>(Q + SB, rsc, invc));
 }
 
 // Pull and collide one cell (x, y, z) from src into dst.
@@ -954,7 +959,8 @@ __global__ void __launch_bounds__(256) k_encode(const double *__restrict__ in, S
     if (t >= N * Q2) return;
     const int i = (int)(t / N);
     const long c = t - (long)i * N;
-    pop[(long)i * p.ds + c] = Codec<S>::enc((RealT<S>)in[t], ref_at<D, S>(p, i, c));
+    const float4 rs = ref_state_at<S>(p, c);
+    pop[(long)i * p.ds + c] = Codec<S>::enc((RealT<S>)in[t], ref_enc<D, S>(i, rs, ref_inv_of<S, RealT<S>>(rs)));
 }
 
 // Validate initial fields: rho > 0, b rho < 1, T > 0 and finite.
@@ -969,21 +975,22 @@ static __global__ void __launch_bounds__(256) k_validate(const double *__restric
 }
 
 // Reference density of every cell = sum of its stored (decoded, FP64) f.
-// 16-bit deviation storage: reference state (rho_ref, theta_ref) of every
-// cell from initial fields (rho, T).
-static __global__ void __launch_bounds__(256) k_ref_from_fields(const double *__restrict__ rho,
-                                                                const double *__restrict__ T, long N, double Rg,
-                                                                double b, float2 *__restrict__ refst)
+// 16-bit deviation storage: reference state of every cell (ref_state_of)
+// from initial fields (rho, T).
+template <int D>
+__global__ void __launch_bounds__(256) k_ref_from_fields(const double *__restrict__ rho, const double *__restrict__ T,
+                                                         long N, double Rg, double b, float4 *__restrict__ refst)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
-    refst[t] = make_float2((float)rho[t], (float)(Rg * T[t] / (1.0 - b * rho[t])));
+    const double RT = Rg * T[t];
+    refst[t] = ref_state_of<D>(rho[t], RT / (1.0 - b * rho[t]), 1.5 * RT);
 }
 
 // The same from populations f, g at rest in the cell's own frame: rho = sum f,
 // j = sum c f, K = sum g/rho - |j|^2/(2 rho^2) = (3/2) RT.
 template <int D>
-__device__ inline float2 ref_state(const double *f, const double *g, double b)
+__device__ inline float4 ref_state(const double *f, const double *g, double b)
 {
     constexpr int Q = Lat<D>::Q;
     double rho = 0.0, e = 0.0, j[3] = {0.0, 0.0, 0.0};
@@ -995,13 +1002,13 @@ __device__ inline float2 ref_state(const double *f, const double *g, double b)
         j[2] += cz_d<D>(i) * f[i];
     }
     const double K = e / rho - 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / (rho * rho);
-    return make_float2((float)rho, (float)((2.0 / 3.0) * K / (1.0 - b * rho)));
+    return ref_state_of<D>(rho, (2.0 / 3.0) * K / (1.0 - b * rho), K);
 }
 
 // From decoded populations in the dense host layout ([Q][N] f, then g).
 template <int D>
 __global__ void __launch_bounds__(256) k_ref_from_pops(const double *__restrict__ pops, long N, double b,
-                                                       float2 *__restrict__ refst)
+                                                       float4 *__restrict__ refst)
 {
     constexpr int Q = Lat<D>::Q;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1020,7 +1027,7 @@ __global__ void __launch_bounds__(256) k_ref_from_pops(const double *__restrict_
 // cell's reference).  p.refst is the old state; refst receives the new one
 // (the same array).
 template <int D, int S>
-__global__ void __launch_bounds__(256) k_rereference(StoreT<S> *__restrict__ pop, float2 *refst,
+__global__ void __launch_bounds__(256) k_rereference(StoreT<S> *__restrict__ pop, float4 *refst,
                                                      StepParams<RealT<S>> p)
 {
     constexpr int Q = Lat<D>::Q;
@@ -1031,8 +1038,9 @@ __global__ void __launch_bounds__(256) k_rereference(StoreT<S> *__restrict__ pop
         f[i] = (double)Codec<S>::dec(pop[(long)i * p.ds + t], ref_at<D, S>(p, i, t));
         g[i] = (double)Codec<S>::dec(pop[(long)(Q + i) * p.ds + t], ref_at<D, S>(p, Q + i, t));
     }
-    const float2 rs = ref_state<D>(f, g, (double)p.b);
+    const float4 rs = ref_state<D>(f, g, (double)p.b);
     refst[t] = rs;
+    const RefInv<RealT<S>> inv = ref_inv_of<S, RealT<S>>(rs);
     // re-encode keeping the cell's mass and energy: rest + opposite pair close
     // the balances as in the collision
     constexpr int REST = (Q - 1) / 2, SA = Q - 1, SB = 0;
@@ -1044,17 +1052,17 @@ __global__ void __launch_bounds__(256) k_rereference(StoreT<S> *__restrict__ pop
         mf += f[i];
         mg += g[i];
         if (i == REST || i == SA || i == SB) continue;
-        const Ref<R> rf = ref_value<D, R>(i, rs, p.b), rg = ref_value<D, R>(Q + i, rs, p.b);
+        const Ref<R> rf = ref_enc<D, S>(i, rs, inv), rg = ref_enc<D, S>(Q + i, rs, inv);
         const StoreT<S> fq = Codec<S>::enc((R)f[i], rf), gq = Codec<S>::enc((R)g[i], rg);
         pops.st(i, cb, fq);
         pops.st(Q + i, cb, gq);
         sf += (double)Codec<S>::dec(fq, rf);
         sg += (double)Codec<S>::dec(gq, rg);
     }
-    close_three<S>(pops, cb, REST, SA, SB, mf - sf, (R)f[SA], (R)f[SB], ref_value<D, R>(REST, rs, p.b),
-                   ref_value<D, R>(SA, rs, p.b), ref_value<D, R>(SB, rs, p.b));
-    close_three<S>(pops, cb, Q + REST, Q + SA, Q + SB, mg - sg, (R)g[SA], (R)g[SB], ref_value<D, R>(Q + REST, rs, p.b),
-                   ref_value<D, R>(Q + SA, rs, p.b), ref_value<D, R>(Q + SB, rs, p.b));
+    close_three<S>(pops, cb, REST, SA, SB, mf - sf, (R)f[SA], (R)f[SB], ref_enc<D, S>(REST, rs, inv),
+                   ref_enc<D, S>(SA, rs, inv), ref_enc<D, S>(SB, rs, inv));
+    close_three<S>(pops, cb, Q + REST, Q + SA, Q + SB, mg - sg, (R)g[SA], (R)g[SB], ref_enc<D, S>(Q + REST, rs, inv),
+                   ref_enc<D, S>(Q + SA, rs, inv), ref_enc<D, S>(Q + SB, rs, inv));
 }
 
 static __global__ void __launch_bounds__(256) k_f64_to_f32(const double *__restrict__ in, float *__restrict__ out, long n)
