@@ -132,8 +132,10 @@ def main():
     ms = 1e3 * dt / args.steps
     mlups = cells * args.steps / dt / 1e6
 
-    # kernel durations with HIP events on the lattice's stream
-    t_mom, t_col = L.profile_step(20)
+    # kernel durations with HIP events on the lattice's stream: the one-pass
+    # step's collision (which also pushes the next moments) and the fix-up
+    # that completes those moments
+    t_fix, t_col = L.profile_step(20)
     Q, s = 27, 4
     alg_bytes = 4 * Q * s * cells          # f and g, each read once and written once
     achieved = alg_bytes / (t_col * 1e-3) / 1e9
@@ -160,8 +162,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_collide",
-                     "kernel_ms": round(t_col, 4), "moments_kernel_ms": round(t_mom, 4),
+                     "kernel": "k_collide_zm (one-pass: stream, collide, push next moments)",
+                     "kernel_ms": round(t_col, 4), "fixup_kernel": "k_push_fixup",
+                     "fixup_kernel_ms": round(t_fix, 4),
                      "alg_bytes_per_launch": alg_bytes,
                      "step_effective_GBps": round(step_eff, 1),
                      "copy_probe_GBps": round(copy_gbs, 1)},

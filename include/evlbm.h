@@ -60,7 +60,10 @@ enum {
     EVLBM_OPT_SPHI = 1,        /* sign in front of the first term of eq. correction_u (default -1) */
     EVLBM_OPT_CHECK_EVERY = 4, /* scan for non-finite densities every K steps (0 = never) */
     EVLBM_OPT_USE_GRAPH = 5,   /* 1: replay step chunks from a captured hipGraph (default 1) */
-    EVLBM_OPT_REREF_EVERY = 6  /* 16-bit storage: re-reference every K steps (0 = never; default 100) */
+    EVLBM_OPT_REREF_EVERY = 6, /* 16-bit storage: re-reference every K steps (0 = never; default 100) */
+    EVLBM_OPT_PUSH_MOMENTS = 7 /* D3Q27 with FP32 or FP64 storage: 1 = one-pass step, the collision pushes
+                                  the next moments (default 1); 0 = two-pass step, the moments are pulled
+                                  again before each collision (always so for D2Q9 and 16-bit storage) */
 };
 
 enum { EVLBM_MEASURE_SLAB = 1, EVLBM_MEASURE_DROPLET = 2 };
@@ -144,18 +147,23 @@ int evlbm_get_populations(evlbm_t h, void *f, void *g, int where);
 int evlbm_set_populations(evlbm_t h, const void *f, const void *g, int where);
 
 /* Bit-exact dump of the stored populations, dense [2Q][N], after a one-line
- * JSON header (format evlbm-3: lattice, storage, sizes, parameters, step,
- * byte count), followed for 16-bit storage by the per-cell reference state
- * as four FP32 values per cell.  Load restores all of it into a handle
- * of the same lattice, sizes and storage.  Errors: EIO (open, read, write,
- * bad header, wrong byte count), EINVAL (null argument, different lattice). */
+ * JSON header (format evlbm-4: lattice, storage, sizes, parameters, step,
+ * byte counts), followed for 16-bit storage by the per-cell reference state
+ * as four FP32 values per cell, and for the one-pass D3Q27 step by the
+ * moment field rho, j, e ([D+2][N] in the arithmetic precision), which that
+ * step carries from one step to the next.  Load restores all of it into a
+ * handle of the same lattice, sizes and storage, so the run resumes bit for
+ * bit.  Errors: EIO (open, read, write, bad header, wrong byte count),
+ * EINVAL (null argument, different lattice). */
 int evlbm_checkpoint_save(evlbm_t h, const char *path);
 int evlbm_checkpoint_load(evlbm_t h, const char *path);
 
 /* Time the two kernels of a step with HIP events on the handle's stream:
  * runs nsteps real steps (launched one by one, no graph) and returns the
- * average durations in milliseconds: out[0] = pulled-moment kernel,
- * out[1] = stencil + collision kernel.  Blocks.
+ * average durations in milliseconds: out[1] = stencil + collision kernel,
+ * out[0] = the other kernel of the step: the pulled-moment kernel of the
+ * two-pass step, or the fix-up of the pushed moments of the one-pass D3Q27
+ * step (EVLBM_OPT_PUSH_MOMENTS).  Blocks.
  * Errors: EINVAL (nsteps outside 1..4096), ESTATE, EHIP. */
 int evlbm_profile_step(evlbm_t h, int nsteps, double out[2]);
 

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libevlbm.so")
 D2Q9, D3Q27 = 2, 3
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 HOST_F64, DEVICE_F32, DEVICE_F64 = 0, 1, 2
-OPT_SPHI, OPT_CHECK_EVERY, OPT_USE_GRAPH, OPT_REREF_EVERY = 1, 4, 5, 6
+OPT_SPHI, OPT_CHECK_EVERY, OPT_USE_GRAPH, OPT_REREF_EVERY, OPT_PUSH_MOMENTS = 1, 4, 5, 6, 7
 MEASURE_SLAB, MEASURE_DROPLET = 1, 2
 STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE", -6: "EIO", -7: "ENONPHYS"}

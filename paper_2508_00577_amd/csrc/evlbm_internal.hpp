@@ -14,7 +14,9 @@ struct evlbm_lattice {
     hipStream_t stream = nullptr;
     void *buf[2] = {nullptr, nullptr};  // population buffers, f then g: 2Q arrays of N cells, ds apart
     int cur = 0;                        // buffer holding the current state
-    void *m = nullptr;                  // pulled moments rho, j (D), e: [(D+2)][N]
+    void *m = nullptr;                  // pulled moments rho, j (D), e: [(D+2)][N] of the current state
+    void *m_alt = nullptr;              // D3Q27 one-pass step: the next state's moments (swapped with m)
+    void *shell = nullptr;              // D3Q27 one-pass step: partial moment sums around each tile chunk
     void *lap = nullptr;                // readout scratch: lap rho [N]
     float4 *refst = nullptr;            // 16-bit deviation storage: reference state per cell [N]
     void *scratch = nullptr;            // I/O and reduction scratch
@@ -24,6 +26,7 @@ struct evlbm_lattice {
     int64_t check_every = 0;
     int64_t reref_every = 100;           // 16-bit storage: re-reference period (0 = never)
     bool use_graph = true;
+    bool push = true;                    // D3Q27: moments pushed by the collision (one-pass step)
     // state
     int64_t step = 0;
     bool initialized = false;
@@ -37,7 +40,7 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int ensure_scratch(evlbm_lattice *h, size_t bytes);
 void refresh_moments(evlbm_lattice *h);
-void launch_step(evlbm_lattice *h);
+void launch_step(evlbm_lattice *h, hipEvent_t between = nullptr);
 int run_steps(evlbm_lattice *h, int64_t n);
 int scan_nonfinite(evlbm_lattice *h);
 int rereference(evlbm_lattice *h);

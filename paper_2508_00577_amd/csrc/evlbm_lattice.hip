@@ -84,18 +84,49 @@ struct Ops {
     static constexpr int TX = (S == EVLBM_F64) ? 16 : 64;
     static constexpr int TY = (S == EVLBM_F64) ? 8 : 4;
     static constexpr int ZC = 32;
+    // the one-pass step (FP32 and FP64 storage: with 16-bit storage the
+    // collision's registers leave no room for the pushed sums at 2 waves per SIMD)
+    static constexpr bool PUSH_OK = D == 3 && (S == EVLBM_F32 || S == EVLBM_F64);
+    static long shell_elems(const evlbm_lattice *h)
+    {
+        const long nb = (long)((h->nx + TX - 1) / TX) * ((h->ny + TY - 1) / TY) * ((h->nz + ZC - 1) / ZC);
+        return nb * 5 * Shell<TX, TY, ZC>::SIZE;
+    }
+
+    template <bool PUSH>
+    static void collide_zm(evlbm_lattice *h, const void *src, void *dst)
+    {
+        const int nbx = (h->nx + TX - 1) / TX, nby = (h->ny + TY - 1) / TY, nbz = (h->nz + ZC - 1) / ZC;
+        R *mn = PUSH ? (R *)h->m_alt : nullptr, *sh = PUSH ? (R *)h->shell : nullptr;
+        // buffer addressing while every offset into one population (f or g) stays below 2^32
+        if ((double)27 * h->ds * sizeof(T) < 4294967296.0)
+            hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true, PUSH>), dim3(nbx * nby * nbz), dim3(TX, TY), 0,
+                               h->stream, (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby,
+                               mn, sh);
+        else
+            hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, false, PUSH>), dim3(nbx * nby * nbz), dim3(TX, TY), 0,
+                               h->stream, (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby,
+                               mn, sh);
+    }
+
+    // D3Q27 one-pass step: collision pushing the next moments into m_alt and
+    // the shell, then the fix-up that completes m_alt (event `between` is
+    // recorded between the two when given)
+    static void collide_push(evlbm_lattice *h, const void *src, void *dst, hipEvent_t between)
+    {
+        if constexpr (PUSH_OK) {
+            collide_zm<true>(h, src, dst);
+            if (between) (void)hipEventRecord(between, h->stream);
+            const int nbx = (h->nx + TX - 1) / TX, nby = (h->ny + TY - 1) / TY, nbz = (h->nz + ZC - 1) / ZC;
+            hipLaunchKernelGGL((k_push_fixup<R, TX, TY, ZC>), dim3(nbx * nby * nbz), dim3(TX, TY), 0, h->stream,
+                               (R *)h->m_alt, (const R *)h->shell, h->nx, h->ny, h->nz, nbx, nby, nbz);
+        }
+    }
 
     static void collide(evlbm_lattice *h, const void *src, void *dst)
     {
         if constexpr (D == 3) {
-            const int nbx = (h->nx + TX - 1) / TX, nby = (h->ny + TY - 1) / TY, nbz = (h->nz + ZC - 1) / ZC;
-            // buffer addressing while every offset into one population (f or g) stays below 2^32
-            if ((double)27 * h->ds * sizeof(T) < 4294967296.0)
-                hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true>), dim3(nbx * nby * nbz), dim3(TX, TY), 0,
-                                   h->stream, (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby);
-            else
-                hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, false>), dim3(nbx * nby * nbz), dim3(TX, TY), 0,
-                                   h->stream, (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby);
+            collide_zm<false>(h, src, dst);
         } else {
             dim3 grid((h->nx + BX - 1) / BX, (h->ny + BY - 1) / BY, (h->nz + BZ - 1) / BZ);
             hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ>), grid, dim3(BX, BY, BZ), 0, h->stream, (const T *)src,
@@ -185,6 +216,17 @@ struct RunMoments {
 template <int D, int S>
 struct RunCollide {
     static void run(evlbm_lattice *h, const void *src, void *dst) { Ops<D, S>::collide(h, src, dst); }
+};
+template <int D, int S>
+struct RunCollidePush {
+    static void run(evlbm_lattice *h, const void *src, void *dst, hipEvent_t ev)
+    {
+        Ops<D, S>::collide_push(h, src, dst, ev);
+    }
+};
+template <int D, int S>
+struct RunShellElems {
+    static void run(evlbm_lattice *h, long *n) { *n = Ops<D, S>::PUSH_OK ? Ops<D, S>::shell_elems(h) : 0; }
 };
 template <int D, int S>
 struct RunInit {
@@ -300,14 +342,26 @@ int scan_nonfinite(evlbm_lattice *h)
     return EVLBM_OK;
 }
 
-// One step: moments of the current buffer, collision into the other.
-void launch_step(evlbm_lattice *h)
+// Does the step push the next moments (D3Q27 one-pass step)?
+static bool pushes(const evlbm_lattice *h) { return h->D == 3 && h->push && h->shell != nullptr; }
+
+// One step: moments of the current buffer, collision into the other.  The
+// one-pass D3Q27 step also leaves the moments of the new state in m_alt,
+// which becomes m.
+void launch_step(evlbm_lattice *h, hipEvent_t between)
 {
     refresh_moments(h);
     const int nxt = 1 - h->cur;
-    dispatch<RunCollide>(h, (const void *)h->buf[h->cur], h->buf[nxt]);
+    if (pushes(h)) {
+        dispatch<RunCollidePush>(h, (const void *)h->buf[h->cur], h->buf[nxt], between);
+        std::swap(h->m, h->m_alt);
+        h->m_valid = true;
+    } else {
+        if (between) (void)hipEventRecord(between, h->stream);
+        dispatch<RunCollide>(h, (const void *)h->buf[h->cur], h->buf[nxt]);
+        h->m_valid = false;
+    }
     h->cur = nxt;
-    h->m_valid = false;
     h->step++;
 }
 
@@ -336,10 +390,14 @@ int run_steps(evlbm_lattice *h, int64_t n)
         return EVLBM_OK;
     }
     const int par = h->cur;
+    // The one-pass step keeps the moments current, so its graph starts from
+    // valid moments; the two-pass graph computes them itself.
+    const bool push = pushes(h);
+    if (push) refresh_moments(h);
     if (!h->graph_exec_par[par]) {
         const int cur0 = h->cur;
         const int64_t step0 = h->step;
-        h->m_valid = false;
+        h->m_valid = push;
         hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         for (int k = 0; k < GRAPH_STEPS; ++k) launch_step(h);
@@ -347,7 +405,7 @@ int run_steps(evlbm_lattice *h, int64_t n)
         e = hipStreamEndCapture(h->stream, &g);
         h->cur = cur0;
         h->step = step0;
-        h->m_valid = false;
+        h->m_valid = push;
         if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
         hipGraphExec_t ex = nullptr;
         e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -361,7 +419,7 @@ int run_steps(evlbm_lattice *h, int64_t n)
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     }
     h->step += reps * GRAPH_STEPS;
-    h->m_valid = false;
+    h->m_valid = push;
     for (int64_t k = reps * GRAPH_STEPS; k < n; ++k) launch_step(h);
     return EVLBM_OK;
 }
@@ -417,6 +475,12 @@ int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream,
         }
     }
     e = hipMalloc(&h->m, m_bytes);
+    long shell_n = 0;
+    dispatch<RunShellElems>(h, &shell_n);
+    if (e == hipSuccess && shell_n > 0) {
+        e = hipMalloc(&h->m_alt, m_bytes);
+        if (e == hipSuccess) e = hipMalloc(&h->shell, (size_t)shell_n * real_bytes(storage));
+    }
     if (e == hipSuccess) e = hipMalloc(&h->lap, (size_t)h->N * real_bytes(storage));
     if (e == hipSuccess && (storage == EVLBM_F16DEV || storage == EVLBM_BF16DEV))
         e = hipMalloc(&h->refst, (size_t)h->N * sizeof(float4));
@@ -436,6 +500,8 @@ int evlbm_destroy(evlbm_t h)
     for (int k = 0; k < 2; ++k)
         if (h->buf[k]) hipFree(h->buf[k]);
     if (h->m) hipFree(h->m);
+    if (h->m_alt) hipFree(h->m_alt);
+    if (h->shell) hipFree(h->shell);
     if (h->lap) hipFree(h->lap);
     if (h->refst) hipFree(h->refst);
     if (h->scratch) hipFree(h->scratch);
@@ -493,6 +559,10 @@ int evlbm_set_option(evlbm_t h, int key, double value)
     case EVLBM_OPT_REREF_EVERY:
         if (value < 0) return fail(EVLBM_EINVAL, "re-reference period must be >= 0");
         h->reref_every = (int64_t)value;
+        break;
+    case EVLBM_OPT_PUSH_MOMENTS:
+        h->push = value != 0.0;
+        h->m_valid = false;
         break;
     default:
         return fail(EVLBM_EINVAL, "unknown option %d", key);
@@ -741,27 +811,35 @@ int evlbm_checkpoint_save(evlbm_t h, const char *path)
     if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
     const size_t es = store_bytes(h->storage), row = (size_t)h->N * es;
     const size_t bytes = row * 2 * h->Q;
-    std::vector<char> host(bytes);
+    // The one-pass step carries its moment field from step to step; saving it
+    // makes a resumed run continue bit for bit (moments pulled again would
+    // differ in rounding).
+    const bool with_m = pushes(h);
+    const size_t m_bytes = with_m ? (size_t)h->N * (h->D + 2) * real_bytes(h->storage) : 0;
+    if (with_m) refresh_moments(h);
+    std::vector<char> host(bytes), hm(m_bytes);
     hipError_t e = hipStreamSynchronize(h->stream);
     // dense [2Q][N] on disk: one row per direction array
     if (e == hipSuccess)
         e = hipMemcpy2D(host.data(), row, h->buf[h->cur], (size_t)h->ds * es, row, 2 * h->Q, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && with_m) e = hipMemcpy(hm.data(), h->m, m_bytes, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "copying populations");
     FILE *fp = fopen(path, "wb");
     if (!fp) return fail(EVLBM_EIO, "cannot open %s", path);
     char hdr[512];
     int n = snprintf(hdr, sizeof(hdr),
-                     "{\"format\":\"evlbm-3\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "{\"format\":\"evlbm-4\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%.17g,\"a\":%.17g,\"b\":%.17g,\"kappa\":%.17g,\"tau\":%.17g,\"lambda\":%.17g,"
-                     "\"sphi\":%.17g,\"step\":%lld,\"bytes\":%zu}\n",
+                     "\"sphi\":%.17g,\"step\":%lld,\"bytes\":%zu,\"moment_bytes\":%zu}\n",
                      h->D, h->nx, h->ny, h->nz, h->storage, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi,
-                     (long long)h->step, bytes);
+                     (long long)h->step, bytes, m_bytes);
     bool ok = fwrite(hdr, 1, n, fp) == (size_t)n && fwrite(host.data(), 1, bytes, fp) == bytes;
     if (ok && h->refst) {  // the 16-bit reference state of every cell
         std::vector<float4> r((size_t)h->N);
         e = hipMemcpy(r.data(), h->refst, sizeof(float4) * h->N, hipMemcpyDeviceToHost);
         ok = e == hipSuccess && fwrite(r.data(), sizeof(float4), h->N, fp) == (size_t)h->N;
     }
+    if (ok && with_m) ok = fwrite(hm.data(), 1, m_bytes, fp) == m_bytes;
     ok = (fclose(fp) == 0) && ok;
     if (!ok) return fail(EVLBM_EIO, "writing %s failed", path);
     return EVLBM_OK;
@@ -780,13 +858,13 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
     int D = 0, nx = 0, ny = 0, nz = 0, st = -1;
     long long step = 0;
     double R, a, b, kappa, tau, lam, sphi;
-    size_t bytes = 0;
+    size_t bytes = 0, m_bytes = 0;
     int got = sscanf(hdr,
-                     "{\"format\":\"evlbm-3\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "{\"format\":\"evlbm-4\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%lg,\"a\":%lg,\"b\":%lg,\"kappa\":%lg,\"tau\":%lg,\"lambda\":%lg,"
-                     "\"sphi\":%lg,\"step\":%lld,\"bytes\":%zu}",
-                     &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &step, &bytes);
-    if (got != 14) {
+                     "\"sphi\":%lg,\"step\":%lld,\"bytes\":%zu,\"moment_bytes\":%zu}",
+                     &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &step, &bytes, &m_bytes);
+    if (got != 15) {
         fclose(fp);
         return fail(EVLBM_EIO, "bad checkpoint header in %s", path);
     }
@@ -806,6 +884,13 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
         r.resize((size_t)h->N);
         ok = fread(r.data(), sizeof(float4), h->N, fp) == (size_t)h->N;
     }
+    const size_t m_need = (size_t)h->N * (h->D + 2) * real_bytes(h->storage);
+    if (m_bytes != 0 && m_bytes != m_need) {
+        fclose(fp);
+        return fail(EVLBM_EIO, "checkpoint %s holds %zu moment bytes, expected %zu", path, m_bytes, m_need);
+    }
+    std::vector<char> hm(m_bytes);
+    if (ok && m_bytes) ok = fread(hm.data(), 1, m_bytes, fp) == m_bytes;
     fclose(fp);
     if (!ok) return fail(EVLBM_EIO, "truncated checkpoint %s", path);
     if (h->refst) {
@@ -823,9 +908,15 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
     hipError_t e =
         hipMemcpy2D(h->buf[0], (size_t)h->ds * es, host.data(), row, row, 2 * h->Q, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "copying populations");
+    // the saved moment field is used only by a handle taking the one-pass step
+    const bool use_m = m_bytes != 0 && pushes(h);
+    if (use_m) {
+        e = hipMemcpy(h->m, hm.data(), m_bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "copying moments");
+    }
     h->step = step;
     h->initialized = true;
-    h->m_valid = false;
+    h->m_valid = use_m;
     invalidate_graph(h);
     return EVLBM_OK;
 }
@@ -839,23 +930,27 @@ int evlbm_profile_step(evlbm_t h, int nsteps, double out[2])
     for (auto &x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
     if (e == hipSuccess) {
+        // two-pass step: [moments] [collision]; one-pass: [collision] [fix-up]
+        const bool push = pushes(h);
         for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
             e = hipEventRecord(ev[3 * k], h->stream);
-            h->m_valid = false;
-            refresh_moments(h);
-            if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], h->stream);
-            launch_step(h);
+            if (!push) {
+                h->m_valid = false;
+                refresh_moments(h);
+            }
+            launch_step(h, ev[3 * k + 1]);
             if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 2], h->stream);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     }
     double tm = 0.0, tc = 0.0;
+    const bool push = pushes(h);
     for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
         float a = 0.f, b = 0.f;
         e = hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
         if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
-        tm += a;
-        tc += b;
+        tm += push ? b : a;
+        tc += push ? a : b;
     }
     for (auto &x : ev)
         if (x) (void)hipEventDestroy(x);

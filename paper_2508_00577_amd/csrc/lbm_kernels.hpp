@@ -129,33 +129,46 @@ __device__ inline void pull_pops(const A &pops, const PullOffsets &o, StoreT<S> 
 // Store the rest direction r and the opposite pair a, b of a cell so that
 // their three stored values sum to `total` (exact FP64) up to the pair's own
 // rounding: r gets total - na - nb, the pair its updates na, nb plus half of
-// the rest's rounding residual each (b also absorbs a's rounding).
+// the rest's rounding residual each (b also absorbs a's rounding).  The
+// values the three stored words decode to are returned in out (r, a, b).
 template <int S, class A>
 __device__ inline void close_three(const A &pops, unsigned cell, int r, int a, int b, double total, RealT<S> na,
-                                   RealT<S> nb, Ref<RealT<S>> qr, Ref<RealT<S>> qa, Ref<RealT<S>> qb)
+                                   RealT<S> nb, Ref<RealT<S>> qr, Ref<RealT<S>> qa, Ref<RealT<S>> qb,
+                                   RealT<S> out[3])
 {
     using R = RealT<S>;
     const StoreT<S> vr = Codec<S>::enc((R)(total - (double)na - (double)nb), qr);
-    const double pair = total - (double)Codec<S>::dec(vr, qr);        // what a + b must carry
+    out[0] = Codec<S>::dec(vr, qr);
+    const double pair = total - (double)out[0];                      // what a + b must carry
     const double half = 0.5 * (pair - (double)na - (double)nb);      // half the rest's residual
     const StoreT<S> va = Codec<S>::enc((R)((double)na + half), qa);
-    const StoreT<S> vb = Codec<S>::enc((R)(pair - (double)Codec<S>::dec(va, qa)), qb);
+    out[1] = Codec<S>::dec(va, qa);
+    const StoreT<S> vb = Codec<S>::enc((R)(pair - (double)out[1]), qb);
+    out[2] = Codec<S>::dec(vb, qb);
     pops.st(r, cell, vr);
     pops.st(a, cell, va);
     pops.st(b, cell, vb);
 }
 
+// Receiver of the values a collision stores, as they decode (the next step
+// pulls exactly these): sink(i, f_i, g_i) once per direction.
+struct NoSink {
+    template <typename R>
+    __device__ inline void operator()(int, R, R) const {}
+};
+
 // Equilibria (eq. feq, f_star, geq, gstar with eq. g_corr), shifted state
 // (eq. def_ustar with Qtilde = 0) and the update eq. pre_LBM for one cell,
 // from its pulled populations (raw stored values fr, gr of pull_pops) into
 // the destination of the accessor at the cell itself (o.ox[1] + o.oy[1] +
-// o.oz[1]).  inv_omb = 1/(1 - b rho).
-template <int D, int S, class A>
+// o.oz[1]).  inv_omb = 1/(1 - b rho).  Every stored direction is also handed
+// to sink, decoded.
+template <int D, int S, class A, class Sink = NoSink>
 __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[], const A &pops,
                                       const StepParams<RealT<S>> &p, const PullOffsets &o, RealT<S> rho,
                                       RealT<S> inv_rho, RealT<S> K, RealT<S> inv_omb, RealT<S> theta,
                                       const RealT<S> u[3], const RealT<S> F[3], const RealT<S> Phi[3],
-                                      const RealT<S> qp[3])
+                                      const RealT<S> qp[3], Sink sink = Sink())
 {
     using R = RealT<S>;
     constexpr int Q = Lat<D>::Q;
@@ -250,15 +263,21 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
         const StoreT<S> gq = Codec<S>::enc(gn, rg);
         pops.st(i, cell, fq);
         pops.st(Q + i, cell, gq);
-        sf += (double)Codec<S>::dec(fq, rf);
-        sg += (double)Codec<S>::dec(gq, rg);
+        const R fd = Codec<S>::dec(fq, rf), gd = Codec<S>::dec(gq, rg);
+        sf += (double)fd;
+        sg += (double)gd;
+        sink(i, fd, gd);
     }
     const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
+    R cf[3], cg[3];
     close_three<S>(pops, cell, REST, SA, SB, mass - sf, fn_a, fn_b, ref_enc<D, S>(REST, rsc, invc),
-                   ref_enc<D, S>(SA, rsc, invc), ref_enc<D, S>(SB, rsc, invc));
+                   ref_enc<D, S>(SA, rsc, invc), ref_enc<D, S>(SB, rsc, invc), cf);
     close_three<S>(pops, cell, Q + REST, Q + SA, Q + SB, energy + uF - sg, gn_a, gn_b,
                    ref_enc<D, S>(Q + REST, rsc, invc), ref_enc<D, S>(Q + SA, rsc, invc),
-                   ref_enc<D, S>(Q + SB, rsc, invc));
+                   ref_enc<D, S>(Q + SB, rsc, invc), cg);
+    sink(REST, cf[0], cg[0]);
+    sink(SA, cf[1], cg[1]);
+    sink(SB, cf[2], cg[2]);
 }
 
 // Pull and collide one cell (x, y, z) from src into dst.
@@ -511,12 +530,78 @@ __device__ inline int xcd_tile(int b, int T)
     return (k / per) * T + j * per + k % per;
 }
 
+// Moments of the next step pushed by the collision (one-pass step).  The
+// next step's rho, j and e of a cell are sums over the values stored at its
+// 27 pull sources (the left-hand side of eq. pre_LBM).  A tile chunk
+// (W x H columns, Zc planes from z0) adds up, per target cell, the part of
+// that sum coming from its own cells.  Targets inside the chunk receive it in
+// the moment field directly; the targets around it (tile + 1 in x, y and z)
+// receive it in the chunk's shell of partial sums, which a fix-up pass adds
+// to the owners of those cells.  Shell slots of one moment:
+//   plane lz in [0, Zc): the tile + 1 ring, RING slots (rows ly = -1 and
+//     ly = H with lx in [-1, W], then columns lx = -1 and lx = W)
+//   planes lz = -1 and lz = Zc: the whole tile + 1 face, FACE slots each.
+template <int TX, int TY, int ZC>
+struct Shell {
+    static constexpr int RING = 2 * (TX + 2) + 2 * TY;
+    static constexpr int FACE = (TX + 2) * (TY + 2);
+    static constexpr int SIZE = ZC * RING + 2 * FACE;
+    __host__ __device__ static int ring(int lx, int ly, int H)
+    {
+        if (ly < 0) return lx + 1;
+        if (ly >= H) return (TX + 2) + lx + 1;
+        return 2 * (TX + 2) + (lx < 0 ? ly : TY + ly);
+    }
+    __host__ __device__ static int face(int lx, int ly) { return (lx + 1) + (TX + 2) * (ly + 1); }
+    __host__ __device__ static int slot(int lx, int ly, int lz, int H, int Zc)
+    {
+        if (lz < 0) return ZC * RING + face(lx, ly);
+        if (lz >= Zc) return ZC * RING + FACE + face(lx, ly);
+        return lz * RING + ring(lx, ly, H);
+    }
+};
+
+// Value of the lane one to the left (right) in the same tile row, 0 at the
+// row's end: the in-row shift of a population with c_x = +1 (-1).  A 64-wide
+// row is one wavefront: a DPP whole-wave shift (wave_shr:1 / wave_shl:1, the
+// vacated lane keeping the old value 0); narrower rows use a permute.
+template <int CTRL>
+__device__ inline float dpp_shift(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ inline double dpp_shift(double v)
+{
+    const int2 w = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_update_dpp(0, w.x, CTRL, 0xf, 0xf, false),
+                                                __builtin_amdgcn_update_dpp(0, w.y, CTRL, 0xf, 0xf, false)));
+}
+template <int TX, typename R>
+__device__ inline R from_left(R v, int tx)
+{
+    if constexpr (TX == 64) return dpp_shift<0x138>(v);  // wave_shr:1, lane t <- t - 1
+    const R w = __shfl_up(v, 1, TX);
+    return tx == 0 ? R(0) : w;
+}
+template <int TX, typename R>
+__device__ inline R from_right(R v, int tx)
+{
+    if constexpr (TX == 64) return dpp_shift<0x130>(v);  // wave_shl:1, lane t <- t + 1
+    const R w = __shfl_down(v, 1, TX);
+    return tx == TX - 1 ? R(0) : w;
+}
+
 // BUF selects the population accessor: raw buffer resources (BufPops, valid
-// while 27 N sizeof(T) < 2^32) or per-direction pointers (PtrPops).
-template <int S, int TX, int TY, int ZC, bool BUF>
+// while 27 N sizeof(T) < 2^32) or per-direction pointers (PtrPops).  PUSH
+// also writes the next step's moments: the chunk's own part into m_next,
+// the rest into its shell (slots of Shell, 5 moments per tile, tiles in
+// their natural order); k_push_fixup completes m_next.
+template <int S, int TX, int TY, int ZC, bool BUF, bool PUSH>
 __global__ void __launch_bounds__(TX *TY)
     k_collide_zm(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
-                 StepParams<RealT<S>> p, int nbx, int nby)
+                 StepParams<RealT<S>> p, int nbx, int nby, RealT<S> *__restrict__ m_next,
+                 RealT<S> *__restrict__ shell)
 {
     using R = RealT<S>;
     using T = StoreT<S>;
@@ -527,11 +612,24 @@ __global__ void __launch_bounds__(TX *TY)
     constexpr int NR3 = (ZT::N3 + ZT::NT - 1) / ZT::NT;  // rho halo values loaded per thread
     constexpr int NR1 = (ZT::N1 + ZT::NT - 1) / ZT::NT;  // field cells per thread
     constexpr unsigned RS = sizeof(R);
+    // bytes per moment array; with buffer addressing (27 ds sizeof(T) < 2^32)
+    // all five arrays of m lie within 32-bit byte offsets of its base
+    const unsigned NB = (unsigned)p.N * RS;
     __shared__ R s_rho[ZT::NRHO][ZT::N3];
     __shared__ R s_lap[ZT::NLAP][ZT::N2];
     __shared__ R s_fld[ZT::NFLD][ZT::NF][ZT::N1];
+    // PUSH: in-row sums (Pf = sum f, Jx = sum c_x f, Pg = sum g) per c_z handed
+    // to the row above (c_y = +1) and below (c_y = -1); the two end lanes'
+    // values leaving the row in x; the ring targets' sums for 3 planes
+    using SH = Shell<TX, TY, ZC>;
+    constexpr int NXR = PUSH ? (TY > 1 ? TY - 1 : 1) : 1;
+    __shared__ R s_xup[NXR][PUSH ? 9 : 1][PUSH ? TX : 1];
+    __shared__ R s_xdn[NXR][PUSH ? 9 : 1][PUSH ? TX : 1];
+    __shared__ R s_edge[2][PUSH ? TY : 1][PUSH ? 9 : 1][2];
+    __shared__ R s_ring[PUSH ? 3 : 1][PUSH ? 5 : 1][PUSH ? SH::RING : 1];
 
-    const int tx = threadIdx.x, ty = threadIdx.y;
+    // a 64-wide row is one wavefront: its row index is wave-uniform
+    const int tx = threadIdx.x, ty = TX == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.y) : threadIdx.y;
     const int tid = tx + TX * ty;
     const int tile = xcd_tile(blockIdx.x, nbx * nby);
     const int x0 = (tile % nbx) * TX, y0 = ((tile / nbx) % nby) * TY;
@@ -541,6 +639,7 @@ __global__ void __launch_bounds__(TX *TY)
     const unsigned plane = (unsigned)p.nx * (unsigned)p.ny;
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < p.nx && y < p.ny;
+    const int W = min(TX, p.nx - x0), H = min(TY, p.ny - y0), Zc = z1 - z0;
     // F and K = (3/2) RT of this thread's own column at planes k (cur) and k+1 (nxt)
     R Fc[3] = {R(0), R(0), R(0)}, Kc = R(0), Fn[3] = {R(0), R(0), R(0)}, Kn = R(0);
     using Pops = typename std::conditional<BUF, BufPops<T, Q>, PtrPops<T>>::type;
@@ -595,11 +694,12 @@ __global__ void __launch_bounds__(TX *TY)
 #pragma unroll
         for (int j = 0; j < NR1; ++j)
 #pragma unroll
-            for (int a = 0; a < 4; ++a) mv[j][a] = ld_at(m + (a + 1) * N, (o1[j] + z1) * RS);
+            for (int a = 0; a < 4; ++a) mv[j][a] = BUF ? ld_at(m, (o1[j] + z1) * RS + (a + 1) * NB)
+                                                       : ld_at(m + (a + 1) * N, (o1[j] + z1) * RS);
     };
     // stages (1)-(3) of iteration k: rho of plane k+3 on tile + 3, lap rho of
     // plane k+2 on tile + 2, force and half-step fields of plane k+1 on tile + 1
-    auto stencil_stages = [&](int k) {
+    auto stencil_stages = [&](int k, auto &&after_first_barrier) {
         {
             R *dstp = s_rho[ring_slot(k + 3, ZT::NRHO)];
 #pragma unroll
@@ -607,6 +707,7 @@ __global__ void __launch_bounds__(TX *TY)
                 if (tid + j * ZT::NT < ZT::N3) dstp[tid + j * ZT::NT] = rv[j];
         }
         __syncthreads();
+        after_first_barrier();
         {
             const R *a = s_rho[ring_slot(k + 1, ZT::NRHO)], *b = s_rho[ring_slot(k + 2, ZT::NRHO)],
                     *c = s_rho[ring_slot(k + 3, ZT::NRHO)];
@@ -667,18 +768,179 @@ __global__ void __launch_bounds__(TX *TY)
     // rho of z0-2..z0+2 and rho of z0-3..z0+3: the pipeline starts 6 planes early.
     for (int k = z0 - 6; k < z0; ++k) {
         load_fields(k);
-        stencil_stages(k);
+        stencil_stages(k, [] {});
 #pragma unroll
         for (int a = 0; a < 3; ++a) Fc[a] = Fn[a];
         Kc = Kn;
     }
     const int xl = min(x, p.nx - 1), yl = min(y, p.ny - 1);
+
+    // PUSH state: the decoded stored values of this cell's collision (zero on
+    // lanes past a ragged edge), this thread's own target sums for planes
+    // k-1, k, k+1 (rho, jx, jy, jz, e), and the ring targets it owns:
+    // bottom row (tx, -1) if ty == 0, top row (tx, H) if ty == H - 1, and for
+    // tid < 2 (H + 2) the column target (-1 or W, tid % (H + 2) - 1).
+    R vf[Q], vg[Q], acc[3][5];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[j][q] = R(0);
+    const bool col_owner = tid < 2 * (H + 2);
+    const int col_side = tid >= H + 2 ? 1 : 0, col_ly = tid - col_side * (H + 2) - 1;
+    const int col_lx = col_side ? W : -1;
+    R *const shell_t = PUSH ? shell + (long)tile * 5 * SH::SIZE : nullptr;
+    if constexpr (PUSH) {
+        for (int t = tid; t < 3 * 5 * SH::RING; t += ZT::NT) (&s_ring[0][0][0])[t] = R(0);
+        __syncthreads();
+    }
+    auto ring_add = [&](int kk, int ri, R f, R jx, R jy, R jz, R g) {
+        R *r = &s_ring[ring_slot(kk, 3)][0][ri];
+        r[0] += f;
+        r[SH::RING] += jx;
+        r[2 * SH::RING] += jy;
+        r[3 * SH::RING] += jz;
+        r[4 * SH::RING] += g;
+    };
+    // write the finished sums of plane kk: own target from a[], ring targets
+    // from s_ring (slot cleared for plane kk + 3)
+    auto finish_plane = [&](int kk, const R a[5]) {
+        const int lz = kk - z0;
+        if (active) {
+            if (lz >= 0 && lz < Zc) {
+                const unsigned c = ((unsigned)x + (unsigned)p.nx * ((unsigned)y + (unsigned)p.ny * (unsigned)kk)) * RS;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    if constexpr (BUF)
+                        st_at(m_next, c + q * NB, a[q]);
+                    else
+                        st_at(m_next + q * N, c, a[q]);
+                }
+            } else {
+                const int sl = SH::slot(tx, ty, lz, H, Zc);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) shell_t[q * SH::SIZE + sl] = a[q];
+            }
+        }
+        auto flush = [&](int lx, int ly) {
+            R *r = &s_ring[ring_slot(kk, 3)][0][SH::ring(lx, ly, H)];
+            const int sl = SH::slot(lx, ly, lz, H, Zc);
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                shell_t[q * SH::SIZE + sl] = r[q * SH::RING];
+                r[q * SH::RING] = R(0);
+            }
+        };
+        if (ty == 0 && tx < W) flush(tx, -1);
+        if (ty == H - 1 && tx < W) flush(tx, H);
+        if (col_owner) flush(col_lx, col_ly);
+    };
+    // push the collided plane k: in-row shifts and sums, the row's own part
+    // into acc, the parts for the rows above and below into LDS
+    auto push_plane = [&](int k) {
+#pragma unroll
+        for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+            for (int cy = -1; cy <= 1; ++cy) {
+                const int im = 3 * (cy + 1) + 9 * (cz + 1), i0 = im + 1, ip = im + 2;  // c_x = -1, 0, +1
+                const R fl = from_left<TX>(vf[ip], tx), fr2 = from_right<TX>(vf[im], tx);
+                const R gl = from_left<TX>(vg[ip], tx), gr2 = from_right<TX>(vg[im], tx);
+                const R Pf = (fl + vf[i0]) + fr2, Jx = fl - fr2, Pg = (gl + vg[i0]) + gr2;
+                const int e = 3 * (cy + 1) + (cz + 1);
+                if (ty < H) {
+                    if (tx == 0) {
+                        s_edge[0][ty][e][0] = vf[im];
+                        s_edge[0][ty][e][1] = vg[im];
+                    }
+                    if (tx == W - 1) {
+                        s_edge[1][ty][e][0] = vf[ip];
+                        s_edge[1][ty][e][1] = vg[ip];
+                    }
+                }
+                if (cy == 0) {
+                    acc[cz + 1][0] += Pf;
+                    acc[cz + 1][1] += Jx;
+                    if (cz != 0) acc[cz + 1][3] += cz > 0 ? Pf : -Pf;
+                    acc[cz + 1][4] += Pg;
+                } else if (cy == 1) {
+                    if (ty < H - 1) {
+                        s_xup[ty][3 * (cz + 1)][tx] = Pf;
+                        s_xup[ty][3 * (cz + 1) + 1][tx] = Jx;
+                        s_xup[ty][3 * (cz + 1) + 2][tx] = Pg;
+                    } else if (ty == H - 1 && tx < W) {
+                        ring_add(k + cz, SH::ring(tx, H, H), Pf, Jx, Pf, cz == 0 ? R(0) : cz > 0 ? Pf : -Pf, Pg);
+                    }
+                } else {
+                    if (ty >= 1 && ty < H) {
+                        s_xdn[ty - 1][3 * (cz + 1)][tx] = Pf;
+                        s_xdn[ty - 1][3 * (cz + 1) + 1][tx] = Jx;
+                        s_xdn[ty - 1][3 * (cz + 1) + 2][tx] = Pg;
+                    }
+                    if (ty == 0 && tx < W)
+                        ring_add(k + cz, SH::ring(tx, -1, H), Pf, Jx, -Pf, cz == 0 ? R(0) : cz > 0 ? Pf : -Pf, Pg);
+                }
+            }
+    };
+    // gather the cross-row parts of source plane k (after the barrier that
+    // follows its push), then plane k - 1 is complete: write it and rotate
+    auto gather_plane = [&](int k) {
+        if (active) {
+#pragma unroll
+            for (int cz = -1; cz <= 1; ++cz) {
+                if (ty >= 1) {  // from the row below, c_y = +1
+                    const R Pf = s_xup[ty - 1][3 * (cz + 1)][tx];
+                    acc[cz + 1][0] += Pf;
+                    acc[cz + 1][1] += s_xup[ty - 1][3 * (cz + 1) + 1][tx];
+                    acc[cz + 1][2] += Pf;
+                    if (cz != 0) acc[cz + 1][3] += cz > 0 ? Pf : -Pf;
+                    acc[cz + 1][4] += s_xup[ty - 1][3 * (cz + 1) + 2][tx];
+                }
+                if (ty + 1 < H) {  // from the row above, c_y = -1
+                    const R Pf = s_xdn[ty][3 * (cz + 1)][tx];
+                    acc[cz + 1][0] += Pf;
+                    acc[cz + 1][1] += s_xdn[ty][3 * (cz + 1) + 1][tx];
+                    acc[cz + 1][2] -= Pf;
+                    if (cz != 0) acc[cz + 1][3] += cz > 0 ? Pf : -Pf;
+                    acc[cz + 1][4] += s_xdn[ty][3 * (cz + 1) + 2][tx];
+                }
+            }
+        }
+        if (col_owner) {  // column and corner targets: values leaving the end lanes
+            const int ri = SH::ring(col_lx, col_ly, H);
+#pragma unroll
+            for (int cz = -1; cz <= 1; ++cz) {
+                R f = R(0), fy = R(0), g = R(0);
+#pragma unroll
+                for (int cy = -1; cy <= 1; ++cy) {
+                    const int row = col_ly - cy;
+                    if (row >= 0 && row < H) {
+                        const R fv = s_edge[col_side][row][3 * (cy + 1) + (cz + 1)][0];
+                        f += fv;
+                        if (cy != 0) fy += cy > 0 ? fv : -fv;
+                        g += s_edge[col_side][row][3 * (cy + 1) + (cz + 1)][1];
+                    }
+                }
+                ring_add(k + cz, ri, f, col_side ? f : -f, fy, cz == 0 ? R(0) : cz > 0 ? f : -f, g);
+            }
+        }
+        finish_plane(k - 1, acc[0]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            acc[0][q] = acc[1][q];
+            acc[1][q] = acc[2][q];
+            acc[2][q] = R(0);
+        }
+    };
+
     for (int k = z0; k < z1; ++k) {
         load_fields(k);
         T fr[Q], gr[Q];
         const PullOffsets po = pull_offsets<3, (int)sizeof(T)>(p.nx, p.ny, p.nz, xl, yl, k);
         pull_pops<3, S>(pops, po, fr, gr);
-        stencil_stages(k);
+        stencil_stages(k, [] {});
+        if constexpr (PUSH) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) vf[i] = vg[i] = R(0);
+        }
         // (4) collide plane k
         if (active) {
             const R *fm[ZT::NF], *f0[ZT::NF], *fp[ZT::NF];
@@ -713,12 +975,105 @@ __global__ void __launch_bounds__(TX *TY)
             qp[0] = p.lambda * (P0 * ring_grad<0, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[0] * Phip);
             qp[1] = p.lambda * (P0 * ring_grad<1, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[1] * Phip);
             qp[2] = p.lambda * (P0 * ring_grad<2, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[2] * Phip);
-            collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, inv_omb, theta, u, F, Phi, qp);
+            if constexpr (PUSH)
+                collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, inv_omb, theta, u, F, Phi, qp,
+                                     [&](int i, R f, R g) {
+                                         vf[i] = f;
+                                         vg[i] = g;
+                                     });
+            else
+                collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, inv_omb, theta, u, F, Phi, qp);
+        }
+        if constexpr (PUSH) {
+            push_plane(k);
+            __syncthreads();
+            gather_plane(k);
         }
         // rotate the column's F, K
 #pragma unroll
         for (int a = 0; a < 3; ++a) Fc[a] = Fn[a];
         Kc = Kn;
+    }
+    if constexpr (PUSH) {
+        // planes z1 - 1 (inside the chunk) and z1 (the face above)
+        finish_plane(z1 - 1, acc[0]);
+        finish_plane(z1, acc[1]);
+    }
+}
+
+// Completes the pushed moments: a cell on a face of its tile chunk gets, in a
+// fixed order, the partial sums that the neighbouring chunks left for it in
+// their shells.  In each axis the candidates are the own chunk, the one
+// before (if the cell is the chunk's first, it lies on that chunk's far side)
+// and the one after (if it is the last; on that chunk's near side); a lattice
+// one chunk wide is its own neighbour, so periodic wrap needs no special case.
+// One workgroup of TX x TY threads per tile chunk (natural order); a thread
+// owns one column of the chunk and visits its face cells.
+template <typename R, int TX, int TY, int ZC>
+__global__ void __launch_bounds__(TX *TY) k_push_fixup(R *__restrict__ m, const R *__restrict__ shell, int nx, int ny,
+                                                       int nz, int nbx, int nby, int nbz)
+{
+    using SH = Shell<TX, TY, ZC>;
+    const int tile = blockIdx.x;
+    const int bx = tile % nbx, by = (tile / nbx) % nby, bz = tile / (nbx * nby);
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * ZC;
+    const int W = min(TX, nx - x0), H = min(TY, ny - y0), Zc = min(ZC, nz - z0);
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    if (tx >= W || ty >= H) return;
+    const unsigned N = (unsigned)nx * (unsigned)ny * (unsigned)nz;
+    // candidates per axis: tile index offset and the cell's local coordinate in that tile
+    int nxc = 1, nyc = 1, txi[3] = {bx, 0, 0}, lxs[3] = {tx, 0, 0}, tyi[3] = {by, 0, 0}, lys[3] = {ty, 0, 0};
+    if (tx == 0) {
+        const int b2 = bx == 0 ? nbx - 1 : bx - 1;
+        txi[nxc] = b2;
+        lxs[nxc++] = min(TX, nx - b2 * TX);
+    }
+    if (tx == W - 1) {
+        txi[nxc] = bx == nbx - 1 ? 0 : bx + 1;
+        lxs[nxc++] = -1;
+    }
+    if (ty == 0) {
+        const int b2 = by == 0 ? nby - 1 : by - 1;
+        tyi[nyc] = b2;
+        lys[nyc++] = min(TY, ny - b2 * TY);
+    }
+    if (ty == H - 1) {
+        tyi[nyc] = by == nby - 1 ? 0 : by + 1;
+        lys[nyc++] = -1;
+    }
+    const bool side = nxc > 1 || nyc > 1;  // on an x or y face: every plane
+    const int bzm = bz == 0 ? nbz - 1 : bz - 1, bzp = bz == nbz - 1 ? 0 : bz + 1;
+    const int Zcm = min(ZC, nz - bzm * ZC);
+    for (int lz = 0; lz < Zc; lz = (side || lz == Zc - 1) ? lz + 1 : Zc - 1) {
+        int nzc = 1, tzi[3] = {bz, 0, 0}, lzs[3] = {lz, 0, 0};
+        if (lz == 0) {
+            tzi[nzc] = bzm;
+            lzs[nzc++] = Zcm;
+        }
+        if (lz == Zc - 1) {
+            tzi[nzc] = bzp;
+            lzs[nzc++] = -1;
+        }
+        if (nzc == 1 && !side) continue;
+        const unsigned cell = (unsigned)(x0 + tx) + (unsigned)nx * ((unsigned)(y0 + ty) + (unsigned)ny * (unsigned)(z0 + lz));
+        R sum[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) sum[q] = m[q * (size_t)N + cell];
+        for (int kz = 0; kz < nzc; ++kz) {
+            const int Zc2 = min(ZC, nz - tzi[kz] * ZC);
+            for (int ky = 0; ky < nyc; ++ky) {
+                const int H2 = min(TY, ny - tyi[ky] * TY);
+                for (int kx = 0; kx < nxc; ++kx) {
+                    if (kx == 0 && ky == 0 && kz == 0) continue;
+                    const R *sh = shell + (size_t)(txi[kx] + nbx * (tyi[ky] + nby * tzi[kz])) * 5 * SH::SIZE +
+                                  SH::slot(lxs[kx], lys[ky], lzs[kz], H2, Zc2);
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) sum[q] += sh[q * SH::SIZE];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 5; ++q) m[q * (size_t)N + cell] = sum[q];
     }
 }
 
@@ -1059,10 +1414,11 @@ __global__ void __launch_bounds__(256) k_rereference(StoreT<S> *__restrict__ pop
         sf += (double)Codec<S>::dec(fq, rf);
         sg += (double)Codec<S>::dec(gq, rg);
     }
+    R cd[3];
     close_three<S>(pops, cb, REST, SA, SB, mf - sf, (R)f[SA], (R)f[SB], ref_enc<D, S>(REST, rs, inv),
-                   ref_enc<D, S>(SA, rs, inv), ref_enc<D, S>(SB, rs, inv));
+                   ref_enc<D, S>(SA, rs, inv), ref_enc<D, S>(SB, rs, inv), cd);
     close_three<S>(pops, cb, Q + REST, Q + SA, Q + SB, mg - sg, (R)g[SA], (R)g[SB], ref_enc<D, S>(Q + REST, rs, inv),
-                   ref_enc<D, S>(Q + SA, rs, inv), ref_enc<D, S>(Q + SB, rs, inv));
+                   ref_enc<D, S>(Q + SA, rs, inv), ref_enc<D, S>(Q + SB, rs, inv), cd);
 }
 
 static __global__ void __launch_bounds__(256) k_f64_to_f32(const double *__restrict__ in, float *__restrict__ out, long n)

@@ -1,0 +1,112 @@
+"""The one-pass D3Q27 step (moments of the next step pushed by the collision,
+completed by the fix-up of the tile-chunk shells) against the two-pass step
+(moments pulled again before every collision), through the C ABI.
+
+Both compute the same sums of the same stored values, in a different order,
+so FP64 runs agree to rounding and the FP32 moment fields agree to a few
+ulps.  The shapes cover several tiles with ragged tails in x, y and z, a
+lattice one tile wide (its own neighbour), single planes, rows and columns,
+and lattices smaller than the stencil halo."""
+import numpy as np
+import pytest
+
+import oracle.thermo as TH
+import synth
+
+pytestmark = pytest.mark.gpu
+ev = pytest.importorskip("paper_2508_00577_amd")
+P = synth.params()
+SQ3 = np.sqrt(3.0)
+
+SHAPES = [(13, 11, 37), (70, 12, 20), (33, 8, 130), (1, 9, 17), (2, 5, 6), (40, 1, 3), (3, 4, 1), (1, 1, 1)]
+
+
+def _state(shape, noise=1e-3, seed=synth.SEED + 11):
+    T0 = 0.85 * synth.T_CRIT
+    rl, rv, _ = TH.coexistence(T0)
+    R = max(0.3 * min(shape), 0.5)
+    return synth.droplet(shape, R, rl, rv, noise=noise, seed=seed), np.full(shape, T0)
+
+
+def _lattice(shape, storage, push, rho, T, graph=True):
+    nz, ny, nx = shape
+    L = ev.Lattice(3, nx, ny, nz, storage=storage)
+    L.set_params(**P)
+    L.set_option(ev.OPT_PUSH_MOMENTS, 1 if push else 0)
+    L.set_option(ev.OPT_USE_GRAPH, 1 if graph else 0)
+    L.init_fields(rho, T)
+    return L
+
+
+def _errs(a, b):
+    (r1, u1, T1), (r2, u2, T2) = a, b
+    return (np.abs(r1 - r2).max() / np.abs(r2).max(), np.abs(u1 - u2).max() * SQ3,
+            np.abs(T1 - T2).max() / np.abs(T2).max())
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_one_pass_matches_two_pass_f64(shape):
+    rho, T = _state(shape)
+    print(f"one-pass vs two-pass f64 {shape}", flush=True)
+    a = _lattice(shape, "f64", True, rho, T)
+    b = _lattice(shape, "f64", False, rho, T)
+    a.step(25)
+    b.step(25)
+    fa, ga = a.get_populations()
+    fb, gb = b.get_populations()
+    ef = np.abs(fa - fb).max() / np.abs(fb).max()
+    eg = np.abs(ga - gb).max() / np.abs(gb).max()
+    e = _errs(a.moments(), b.moments())
+    print(f"  e_f={ef:.2e} e_g={eg:.2e} e_rho={e[0]:.2e} e_u={e[1]:.2e} e_T={e[2]:.2e}", flush=True)
+    assert ef < 1e-12 and eg < 1e-12
+    assert max(e) < 1e-12
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-14), ("f32", 2e-6)])
+@pytest.mark.parametrize("shape", [(13, 11, 37), (70, 12, 20), (2, 5, 6)])
+def test_pushed_moments_equal_pulled(shape, storage, tol):
+    """The moment field the one-pass step carries equals the moments pulled
+    from the stored populations (switching the option off pulls them again)."""
+    rho, T = _state(shape)
+    L = _lattice(shape, storage, True, rho, T)
+    L.step(40)
+    pushed = L.moments()
+    L.set_option(ev.OPT_PUSH_MOMENTS, 0)
+    pulled = L.moments()
+    e = _errs(pushed, pulled)
+    print(f"pushed vs pulled {storage} {shape}: e_rho={e[0]:.2e} e_u={e[1]:.2e} e_T={e[2]:.2e}", flush=True)
+    assert max(e) < tol
+
+
+def test_one_pass_graph_replay_matches_eager():
+    """Captured chunks of one-pass steps give the same bits as eager launches,
+    across chunk boundaries and remainders."""
+    shape = (40, 12, 70)
+    rho, T = _state(shape)
+    a = _lattice(shape, "f32", True, rho, T, graph=True)
+    b = _lattice(shape, "f32", True, rho, T, graph=False)
+    for n in (70, 5, 64, 33):
+        a.step(n)
+        b.step(n)
+    fa, ga = a.get_populations()
+    fb, gb = b.get_populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_one_pass_checkpoint_resume_is_bitwise(storage, tmp_path):
+    shape = (36, 10, 70)
+    rho, T = _state(shape)
+    a = _lattice(shape, storage, True, rho, T)
+    a.step(50)
+    path = tmp_path / "ck3.evlbm"
+    a.checkpoint_save(path)
+    a.step(30)
+    nz, ny, nx = shape
+    b = ev.Lattice(3, nx, ny, nz, storage=storage)
+    b.checkpoint_load(path)
+    assert b.step_count == 50
+    b.step(30)
+    fa, ga = a.get_populations()
+    fb, gb = b.get_populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
