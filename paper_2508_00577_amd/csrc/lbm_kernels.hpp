@@ -563,19 +563,19 @@ struct Shell {
 
 // Value of the lane one to the left (right) in the same tile row, 0 at the
 // row's end: the in-row shift of a population with c_x = +1 (-1).  A 64-wide
-// row is one wavefront: a DPP whole-wave shift (wave_shr:1 / wave_shl:1, the
-// vacated lane keeping the old value 0); narrower rows use a permute.
+// row is one wavefront: a DPP whole-wave shift (wave_shr:1 / wave_shl:1 with
+// bound_ctrl, so the vacated lane reads 0); narrower rows use a permute.
 template <int CTRL>
 __device__ inline float dpp_shift(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL>
 __device__ inline double dpp_shift(double v)
 {
     const int2 w = __builtin_bit_cast(int2, v);
-    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_update_dpp(0, w.x, CTRL, 0xf, 0xf, false),
-                                                __builtin_amdgcn_update_dpp(0, w.y, CTRL, 0xf, 0xf, false)));
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_mov_dpp(w.x, CTRL, 0xf, 0xf, true),
+                                                __builtin_amdgcn_mov_dpp(w.y, CTRL, 0xf, 0xf, true)));
 }
 template <int TX, typename R>
 __device__ inline R from_left(R v, int tx)
@@ -682,20 +682,29 @@ __global__ void __launch_bounds__(TX *TY)
 
     // Every global load of an iteration is issued up front in straight-line
     // code (no branch around any of them, so the compiler's wait counters stay
-    // exact), oldest use first: rho of plane k+3, j and e of plane k+1, then
-    // the populations of plane k; stages (1)-(3) run while the populations are
-    // in flight.  Halo loads use clamped offsets; threads past a ragged edge
-    // pull a valid cell and skip only the stores.
-    R rv[NR3], mv[NR1][4];
-    auto load_fields = [&](int k) {
+    // exact): the populations of plane k, then the moment fields of the next
+    // iteration (rho of plane k+4, j and e of plane k+2), so that stage (1)
+    // finds its inputs loaded one iteration earlier and stages (1)-(3) run
+    // while the populations are in flight.  Halo loads use clamped offsets;
+    // threads past a ragged edge pull a valid cell and skip only the stores.
+    R rv[NR3], mv[NR1][4], rvn[NR3], mvn[NR1][4];
+    auto load_fields = [&](int k, R(&r3)[NR3], R(&r1)[NR1][4]) {
         const unsigned z3 = (unsigned)wrapi(k + 3, p.nz) * plane, z1 = (unsigned)wrapi(k + 1, p.nz) * plane;
 #pragma unroll
-        for (int j = 0; j < NR3; ++j) rv[j] = ld_at(m, (o3[j] + z3) * RS);
+        for (int j = 0; j < NR3; ++j) r3[j] = ld_at(m, (o3[j] + z3) * RS);
 #pragma unroll
         for (int j = 0; j < NR1; ++j)
 #pragma unroll
-            for (int a = 0; a < 4; ++a) mv[j][a] = BUF ? ld_at(m, (o1[j] + z1) * RS + (a + 1) * NB)
+            for (int a = 0; a < 4; ++a) r1[j][a] = BUF ? ld_at(m, (o1[j] + z1) * RS + (a + 1) * NB)
                                                        : ld_at(m + (a + 1) * N, (o1[j] + z1) * RS);
+    };
+    auto next_fields = [&]() {
+#pragma unroll
+        for (int j = 0; j < NR3; ++j) rv[j] = rvn[j];
+#pragma unroll
+        for (int j = 0; j < NR1; ++j)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) mv[j][a] = mvn[j][a];
     };
     // stages (1)-(3) of iteration k: rho of plane k+3 on tile + 3, lap rho of
     // plane k+2 on tile + 2, force and half-step fields of plane k+1 on tile + 1
@@ -766,9 +775,11 @@ __global__ void __launch_bounds__(TX *TY)
 
     // Collision of plane z0 needs the fields of planes z0-1..z0+1, hence lap
     // rho of z0-2..z0+2 and rho of z0-3..z0+3: the pipeline starts 6 planes early.
+    load_fields(z0 - 6, rv, mv);
     for (int k = z0 - 6; k < z0; ++k) {
-        load_fields(k);
+        load_fields(k + 1, rvn, mvn);
         stencil_stages(k, [] {});
+        next_fields();
 #pragma unroll
         for (int a = 0; a < 3; ++a) Fc[a] = Fn[a];
         Kc = Kn;
@@ -778,31 +789,59 @@ __global__ void __launch_bounds__(TX *TY)
     // PUSH state: the decoded stored values of this cell's collision (zero on
     // lanes past a ragged edge), this thread's own target sums for planes
     // k-1, k, k+1 (rho, jx, jy, jz, e), and the ring targets it owns:
-    // bottom row (tx, -1) if ty == 0, top row (tx, H) if ty == H - 1, and for
-    // tid < 2 (H + 2) the column target (-1 or W, tid % (H + 2) - 1).
+    // bottom row (tx, -1) if ty == 0, top row (tx, H) if ty == H - 1, and the
+    // column targets (-1 or W, c % (H + 2) - 1) on c = tid - TX < 2 (H + 2)
+    // (threads of the second row, which own no ring row when TY > 2).
     R vf[Q], vg[Q], acc[3][5];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[j][q] = R(0);
-    const bool col_owner = tid < 2 * (H + 2);
-    const int col_side = tid >= H + 2 ? 1 : 0, col_ly = tid - col_side * (H + 2) - 1;
+    const int col_c = tid - (TY > 2 ? TX : 0);
+    const bool col_owner = col_c >= 0 && col_c < 2 * (H + 2);
+    const int col_side = col_c >= H + 2 ? 1 : 0, col_ly = col_c - col_side * (H + 2) - 1;
     const int col_lx = col_side ? W : -1;
     R *const shell_t = PUSH ? shell + (long)tile * 5 * SH::SIZE : nullptr;
     if constexpr (PUSH) {
         for (int t = tid; t < 3 * 5 * SH::RING; t += ZT::NT) (&s_ring[0][0][0])[t] = R(0);
         __syncthreads();
     }
-    auto ring_add = [&](int kk, int ri, R f, R jx, R jy, R jz, R g) {
-        R *r = &s_ring[ring_slot(kk, 3)][0][ri];
-        r[0] += f;
-        r[SH::RING] += jx;
-        r[2 * SH::RING] += jy;
-        r[3 * SH::RING] += jz;
-        r[4 * SH::RING] += g;
+    // A ring target (lx, ly) takes source plane kk's parts rc for planes
+    // kk-1, kk, kk+1 in one LDS round trip: plane kk-1 is then complete and
+    // goes to the shell (its slot cleared for plane kk+2), the other two stay.
+    auto ring_commit = [&](int kk, int lx, int ly, const R(&rc)[3][5]) {
+        const int ri = SH::ring(lx, ly, H);
+        R *r0 = &s_ring[ring_slot(kk - 1, 3)][0][ri], *r1 = &s_ring[ring_slot(kk, 3)][0][ri],
+          *r2 = &s_ring[ring_slot(kk + 1, 3)][0][ri];
+        R a0[5], a1[5], a2[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            a0[q] = r0[q * SH::RING];
+            a1[q] = r1[q * SH::RING];
+            a2[q] = r2[q * SH::RING];
+        }
+        const int sl = SH::slot(lx, ly, kk - 1 - z0, H, Zc);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            r0[q * SH::RING] = R(0);
+            r1[q * SH::RING] = a1[q] + rc[1][q];
+            r2[q * SH::RING] = a2[q] + rc[2][q];
+            st_at(shell_t, (unsigned)(q * SH::SIZE + sl) * RS, a0[q] + rc[0][q]);
+        }
     };
-    // write the finished sums of plane kk: own target from a[], ring targets
-    // from s_ring (slot cleared for plane kk + 3)
+    // the last two planes of a ring target at the chunk's end
+    auto ring_final = [&](int lx, int ly) {
+        const int ri = SH::ring(lx, ly, H);
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const int kk = z1 - 1 + d;
+            const int sl = SH::slot(lx, ly, kk - z0, H, Zc);
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                st_at(shell_t, (unsigned)(q * SH::SIZE + sl) * RS, s_ring[ring_slot(kk, 3)][q][ri]);
+        }
+    };
+    // write the finished sums of plane kk of the thread's own target
     auto finish_plane = [&](int kk, const R a[5]) {
         const int lz = kk - z0;
         if (active) {
@@ -818,25 +857,14 @@ __global__ void __launch_bounds__(TX *TY)
             } else {
                 const int sl = SH::slot(tx, ty, lz, H, Zc);
 #pragma unroll
-                for (int q = 0; q < 5; ++q) shell_t[q * SH::SIZE + sl] = a[q];
+                for (int q = 0; q < 5; ++q) st_at(shell_t, (unsigned)(q * SH::SIZE + sl) * RS, a[q]);
             }
         }
-        auto flush = [&](int lx, int ly) {
-            R *r = &s_ring[ring_slot(kk, 3)][0][SH::ring(lx, ly, H)];
-            const int sl = SH::slot(lx, ly, lz, H, Zc);
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                shell_t[q * SH::SIZE + sl] = r[q * SH::RING];
-                r[q * SH::RING] = R(0);
-            }
-        };
-        if (ty == 0 && tx < W) flush(tx, -1);
-        if (ty == H - 1 && tx < W) flush(tx, H);
-        if (col_owner) flush(col_lx, col_ly);
     };
     // push the collided plane k: in-row shifts and sums, the row's own part
     // into acc, the parts for the rows above and below into LDS
     auto push_plane = [&](int k) {
+        R rc_dn[3][5], rc_up[3][5];  // parts for the rows below (c_y = -1) and above (c_y = +1) the tile
 #pragma unroll
         for (int cz = -1; cz <= 1; ++cz)
 #pragma unroll
@@ -866,19 +894,28 @@ __global__ void __launch_bounds__(TX *TY)
                         s_xup[ty][3 * (cz + 1)][tx] = Pf;
                         s_xup[ty][3 * (cz + 1) + 1][tx] = Jx;
                         s_xup[ty][3 * (cz + 1) + 2][tx] = Pg;
-                    } else if (ty == H - 1 && tx < W) {
-                        ring_add(k + cz, SH::ring(tx, H, H), Pf, Jx, Pf, cz == 0 ? R(0) : cz > 0 ? Pf : -Pf, Pg);
                     }
+                    rc_up[cz + 1][0] = Pf;
+                    rc_up[cz + 1][1] = Jx;
+                    rc_up[cz + 1][2] = Pf;
+                    rc_up[cz + 1][3] = cz == 0 ? R(0) : cz > 0 ? Pf : -Pf;
+                    rc_up[cz + 1][4] = Pg;
                 } else {
                     if (ty >= 1 && ty < H) {
                         s_xdn[ty - 1][3 * (cz + 1)][tx] = Pf;
                         s_xdn[ty - 1][3 * (cz + 1) + 1][tx] = Jx;
                         s_xdn[ty - 1][3 * (cz + 1) + 2][tx] = Pg;
                     }
-                    if (ty == 0 && tx < W)
-                        ring_add(k + cz, SH::ring(tx, -1, H), Pf, Jx, -Pf, cz == 0 ? R(0) : cz > 0 ? Pf : -Pf, Pg);
+                    rc_dn[cz + 1][0] = Pf;
+                    rc_dn[cz + 1][1] = Jx;
+                    rc_dn[cz + 1][2] = -Pf;
+                    rc_dn[cz + 1][3] = cz == 0 ? R(0) : cz > 0 ? Pf : -Pf;
+                    rc_dn[cz + 1][4] = Pg;
                 }
             }
+        // the first and last rows own the ring rows below and above the tile
+        if (ty == 0 && tx < W) ring_commit(k, tx, -1, rc_dn);
+        if (ty == H - 1 && tx < W) ring_commit(k, tx, H, rc_up);
     };
     // gather the cross-row parts of source plane k (after the barrier that
     // follows its push), then plane k - 1 is complete: write it and rotate
@@ -905,7 +942,7 @@ __global__ void __launch_bounds__(TX *TY)
             }
         }
         if (col_owner) {  // column and corner targets: values leaving the end lanes
-            const int ri = SH::ring(col_lx, col_ly, H);
+            R rc[3][5];
 #pragma unroll
             for (int cz = -1; cz <= 1; ++cz) {
                 R f = R(0), fy = R(0), g = R(0);
@@ -919,8 +956,13 @@ __global__ void __launch_bounds__(TX *TY)
                         g += s_edge[col_side][row][3 * (cy + 1) + (cz + 1)][1];
                     }
                 }
-                ring_add(k + cz, ri, f, col_side ? f : -f, fy, cz == 0 ? R(0) : cz > 0 ? f : -f, g);
+                rc[cz + 1][0] = f;
+                rc[cz + 1][1] = col_side ? f : -f;
+                rc[cz + 1][2] = fy;
+                rc[cz + 1][3] = cz == 0 ? R(0) : cz > 0 ? f : -f;
+                rc[cz + 1][4] = g;
             }
+            ring_commit(k, col_lx, col_ly, rc);
         }
         finish_plane(k - 1, acc[0]);
 #pragma unroll
@@ -931,18 +973,23 @@ __global__ void __launch_bounds__(TX *TY)
         }
     };
 
+    // The populations of plane k+1 are pulled as soon as the collision of
+    // plane k has consumed those of plane k, after the next moment fields, so
+    // they are in flight through the push, the next iteration's stencil
+    // stages and its barriers.  The last iteration pulls plane z1 (a valid
+    // plane, not used).
+    T fr[Q], gr[Q];
+    pull_pops<3, S>(pops, pull_offsets<3, (int)sizeof(T)>(p.nx, p.ny, p.nz, xl, yl, z0), fr, gr);
     for (int k = z0; k < z1; ++k) {
-        load_fields(k);
-        T fr[Q], gr[Q];
         const PullOffsets po = pull_offsets<3, (int)sizeof(T)>(p.nx, p.ny, p.nz, xl, yl, k);
-        pull_pops<3, S>(pops, po, fr, gr);
         stencil_stages(k, [] {});
-        if constexpr (PUSH) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) vf[i] = vg[i] = R(0);
-        }
         // (4) collide plane k
-        if (active) {
+        if (!active) {
+            if constexpr (PUSH) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) vf[i] = vg[i] = R(0);
+            }
+        } else {
             const R *fm[ZT::NF], *f0[ZT::NF], *fp[ZT::NF];
 #pragma unroll
             for (int q = 0; q < ZT::NF; ++q) {
@@ -984,11 +1031,14 @@ __global__ void __launch_bounds__(TX *TY)
             else
                 collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, inv_omb, theta, u, F, Phi, qp);
         }
+        load_fields(k + 1, rvn, mvn);
+        pull_pops<3, S>(pops, pull_offsets<3, (int)sizeof(T)>(p.nx, p.ny, p.nz, xl, yl, k + 1), fr, gr);
         if constexpr (PUSH) {
             push_plane(k);
             __syncthreads();
             gather_plane(k);
         }
+        next_fields();
         // rotate the column's F, K
 #pragma unroll
         for (int a = 0; a < 3; ++a) Fc[a] = Fn[a];
@@ -998,6 +1048,9 @@ __global__ void __launch_bounds__(TX *TY)
         // planes z1 - 1 (inside the chunk) and z1 (the face above)
         finish_plane(z1 - 1, acc[0]);
         finish_plane(z1, acc[1]);
+        if (ty == 0 && tx < W) ring_final(tx, -1);
+        if (ty == H - 1 && tx < W) ring_final(tx, H);
+        if (col_owner) ring_final(col_lx, col_ly);
     }
 }
 
