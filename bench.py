@@ -97,8 +97,19 @@ def cpu_baseline(target_seconds=12.0):
     L.step(n)
     dt = time.perf_counter() - t0
     cells = 64 * 64 * 32
-    return {"value": cells * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"D3Q27 64x64x32 droplet R=12 T/Tc=0.8, FP64, {n + 1} steps ({dt + one:.1f} s)"}
+    threads = oracle.get_threads()
+    # the same sample on one thread, two steps
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        L.step(2)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    return {"value": cells * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "value_1thread": cells * 2 / dt1 / 1e6,
+            "sample": f"D3Q27 64x64x32 droplet R=12 T/Tc=0.8, FP64, {n + 1} steps ({dt + one:.1f} s) on all "
+                      f"threads, then 2 steps ({dt1:.1f} s) on one"}
 
 
 def main():
@@ -209,11 +220,24 @@ def main():
         # workload (density error after `cmp` steps; the full 1e4-step horizon
         # with --long-precision)
         cmp = 10000 if args.long_precision else 1000
+        # FP64 storage on the GPU (held to 1e-10 of the FP64 oracle by the
+        # parity tests; the oracle itself cannot run this lattice) as the
+        # reference each storage's density error is stated against
+        L64 = make_droplet(ev, synth, shape, 40.0 * n / 256, 0.8, "f64")
+        t0 = time.perf_counter()
+        L64.step(cmp)
+        L64.synchronize()
+        extras["f64_MLUPS"] = round(cells * cmp / (time.perf_counter() - t0) / 1e6, 1)
+        r64, _, _ = L64.moments(device=True)
+        r64 = r64.double()
+        del L64
+        torch.cuda.empty_cache()
         ref = make_droplet(ev, synth, shape, 40.0 * n / 256, 0.8, "f32")
         ref.step(cmp)
         r_ref, _, _ = ref.moments(device=True)
         r_ref = r_ref.double()
         del ref
+        extras[f"f32_rho_rel_err_vs_f64_at_{cmp}_steps"] = float(((r_ref - r64).abs().max() / r64.abs().max()).item())
         for st in ("f16dev", "bf16dev"):
             L3 = make_droplet(ev, synth, shape, 40.0 * n / 256, 0.8, st)
             L3.step(cmp)
@@ -224,6 +248,8 @@ def main():
             extras[f"{st}_MLUPS"] = round(cells * 200 / t / 1e6, 1)
             extras[f"{st}_collide_GBps_alg"] = round(4 * Q * 2 * cells / (tc * 1e-3) / 1e9, 1)
             extras[f"{st}_rho_rel_err_vs_f32_at_{cmp}_steps"] = err
+            extras[f"{st}_rho_rel_err_vs_f64_at_{cmp}_steps"] = float(((r3.double() - r64).abs().max() /
+                                                                       r64.abs().max()).item())
             del L3
         torch.cuda.empty_cache()
         # learned warm start (2D 96^2 droplets): train on 12 long runs, then
@@ -237,13 +263,26 @@ def main():
         X, Y = W.training_samples(cases, wshape, p2, steps=40000, rho_c=1.0)
         net, hist = W.train_network(X, Y, synth.xavier_params(), iters=3000, lr=2e-3)
         t_train = time.perf_counter() - t0
-        ws = W.warm_start_study(net, [(15.0, 0.84)], wshape, p2, horizon=100000, check=1000, tol=1e-3)[0]
-        extras["warm_start_96sq_R15_Tr084"] = {
+        held_out = [(15.0, 0.84), (12.5, 0.76), (20.0, 0.8)]
+        study = W.warm_start_study(net, held_out, wshape, p2, horizon=100000, check=1000, tol=1e-3)
+        extras["warm_start_96sq"] = {
             "train_s": round(t_train, 2), "train_loss": [float(hist[0]), float(hist[-1])],
-            "steps_to_1e-3_plain": ws["steps_tanh"], "steps_to_1e-3_mlp_matched": ws["steps_mlp_matched"],
-            "err0_plain": ws["err0_tanh"], "err0_mlp_matched": ws["err0_mlp_matched"],
-            "err_1e5_mlp_matched": ws["err_end_mlp_matched"], "err_1e5_mlp_unmatched": ws["err_end_mlp"],
-            "network_used": ws["mlp_used"]}
+            "cases": [{"R": ws["R"], "Tr": ws["Tr"],
+                       "steps_to_1e-3_plain": ws["steps_tanh"], "steps_to_1e-3_mlp_matched": ws["steps_mlp_matched"],
+                       "err0_plain": ws["err0_tanh"], "err0_mlp_matched": ws["err0_mlp_matched"],
+                       "err_1e5_mlp_matched": ws["err_end_mlp_matched"], "err_1e5_mlp_unmatched": ws["err_end_mlp"],
+                       "network_used": ws["mlp_used"]} for ws in study]}
+        # the tanh fallback outside the network's training box (R in [10, 22], T/Tc in [0.72, 0.88])
+        outside = [(30.0, 0.8), (16.0, 0.6), (16.0, 0.95)]
+        used = []
+        for R, Tr in outside + held_out:
+            Lw = ev.Lattice(2, wshape[2], wshape[1], 1, storage="f32")
+            Lw.set_params(**p2)
+            used.append(bool(Lw.init_droplet(R, Tr, profile="mlp", mlp=net)))
+            del Lw
+        extras["warm_start_96sq"]["fallback"] = {
+            "cases": [list(c) for c in outside + held_out], "network_used": used,
+            "fallbacks": int(sum(not u for u in used))}
         result["extras"] = extras
 
     if not args.no_cpu:

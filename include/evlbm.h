@@ -254,8 +254,15 @@ int evlbm_mlp_forward(evlbm_mlp_t m, const float *X, float *Y, int n);
  * (nullable) at the current parameters; blocks. */
 int evlbm_mlp_grad(evlbm_mlp_t m, const float *X, const float *Y, int n, float *grad, float *loss);
 /* iters full-batch Adam steps with learning rate lr; loss_hist[iters]
- * (nullable) receives the loss before each step; blocks. */
+ * (nullable) receives the loss before each step; blocks.  The network's
+ * trusted (T/Tc, R) box grows to cover the training inputs. */
 int evlbm_mlp_train(evlbm_mlp_t m, const float *X, const float *Y, int n, int iters, float lr, float *loss_hist);
+/* The (T/Tc, R) box the network is trusted on, [tr_lo, tr_hi] x [r_lo, r_hi]:
+ * empty for a new network, the training inputs' box after evlbm_mlp_train;
+ * set it for parameters trained elsewhere.  get: out = {tr_lo, tr_hi, r_lo,
+ * r_hi}.  Errors: EINVAL (null handle, lo > hi). */
+int evlbm_mlp_set_hull(evlbm_mlp_t m, double tr_lo, double tr_hi, double r_lo, double r_hi);
+int evlbm_mlp_get_hull(evlbm_mlp_t m, double out[4]);
 /* Device FP64 density field rho_c * y(T/Tc, R, |x - c|/R) of a lattice of
  * nx*ny*nz cells (nz = 1: 2D distance), enqueued on the network's stream. */
 int evlbm_mlp_density_field(evlbm_mlp_t m, int nx, int ny, int nz, double cx, double cy, double cz, double R,
@@ -264,8 +271,9 @@ int evlbm_mlp_density_field(evlbm_mlp_t m, int nx, int ny, int nz, double cx, do
 /* Initialise a droplet of radius R centred at (cx, cy, cz) at T/Tc = Tr, at
  * rest: TANH = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh((r - R)/width) with
  * the coexistence densities; MLP = the network's profile, falling back to
- * TANH when Tr or R lie outside [0.65, 0.97] x [12, 90] or the radial profile
- * is non-finite, increasing in r or outside [0.5 rho_v, 1.2 rho_l].
+ * TANH when (Tr, R) lies outside the network's trusted box
+ * (evlbm_mlp_set_hull) or the radial profile is non-finite, increasing in r
+ * or outside [0.5 rho_v, 1.2 rho_l].
  * *used_mlp (nullable) tells which was used.  Needs a > 0, b > 0. */
 int evlbm_init_droplet(evlbm_t h, double cx, double cy, double cz, double R, double Tr, int profile, evlbm_mlp_t mlp,
                        double width, int *used_mlp);

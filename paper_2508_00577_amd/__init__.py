@@ -87,6 +87,8 @@ def lib():
         L.evlbm_mlp_forward.argtypes = [_vp, _fp, _fp, ctypes.c_int]
         L.evlbm_mlp_grad.argtypes = [_vp, _fp, _fp, ctypes.c_int, _fp, _fp]
         L.evlbm_mlp_train.argtypes = [_vp, _fp, _fp, ctypes.c_int, ctypes.c_int, ctypes.c_float, _fp]
+        L.evlbm_mlp_set_hull.argtypes = [_vp] + [ctypes.c_double] * 4
+        L.evlbm_mlp_get_hull.argtypes = [_vp, _dp]
         L.evlbm_init_droplet.argtypes = [_vp] + [ctypes.c_double] * 5 + [ctypes.c_int, _vp, ctypes.c_double,
                                                                          ctypes.POINTER(ctypes.c_int)]
         L.evlbm_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)] + [ctypes.POINTER(ctypes.c_int)] * 4
@@ -421,6 +423,15 @@ class MLP:
         p = np.zeros(NPARAM, dtype=np.float32)
         _check(lib().evlbm_mlp_get_params(self._h, _fptr(p), NPARAM))
         return p
+
+    def set_hull(self, tr_lo, tr_hi, r_lo, r_hi):
+        _check(lib().evlbm_mlp_set_hull(self._h, float(tr_lo), float(tr_hi), float(r_lo), float(r_hi)))
+
+    def hull(self):
+        """(tr_lo, tr_hi, r_lo, r_hi): the box of (T/Tc, R) the network is trusted on."""
+        out = np.zeros(4)
+        _check(lib().evlbm_mlp_get_hull(self._h, out.ctypes.data_as(_dp)))
+        return tuple(float(v) for v in out)
 
     def forward(self, X):
         X = _f32(X).reshape(-1, 3)

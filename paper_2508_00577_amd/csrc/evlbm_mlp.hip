@@ -285,6 +285,9 @@ struct evlbm_mlp {
     float *X = nullptr, *Y = nullptr, *G = nullptr, *L = nullptr, *gsum = nullptr, *loss = nullptr;
     long cap = 0;  // samples the work buffers hold
     long t = 0;    // Adam step count
+    // (T/Tc, R) box of the inputs the network was trained on: lo, hi of T/Tc,
+    // then of R (empty until trained or set)
+    double hull[4] = {HUGE_VAL, -HUGE_VAL, HUGE_VAL, -HUGE_VAL};
 };
 
 namespace {
@@ -412,6 +415,12 @@ int evlbm_mlp_train(evlbm_mlp_t m, const float *X, const float *Y, int n, int it
     if (!m || !X || !Y || n <= 0 || iters <= 0 || !(lr > 0)) return fail(EVLBM_EINVAL, "bad arguments");
     int rc = mlp_upload(m, X, Y, n);
     if (rc) return rc;
+    for (int k = 0; k < n; ++k) {  // the trusted box grows to cover the training inputs
+        m->hull[0] = std::fmin(m->hull[0], (double)X[3 * k]);
+        m->hull[1] = std::fmax(m->hull[1], (double)X[3 * k]);
+        m->hull[2] = std::fmin(m->hull[2], (double)X[3 * k + 1]);
+        m->hull[3] = std::fmax(m->hull[3], (double)X[3 * k + 1]);
+    }
     const int nw = (n + ROWS - 1) / ROWS;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     std::vector<float> hist(loss_hist ? iters : 0);
@@ -434,6 +443,23 @@ int evlbm_mlp_train(evlbm_mlp_t m, const float *X, const float *Y, int n, int it
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (dhist) (void)hipFree(dhist);
     if (e != hipSuccess) return hip_fail(e, "network training");
+    return EVLBM_OK;
+}
+
+int evlbm_mlp_set_hull(evlbm_mlp_t m, double tr_lo, double tr_hi, double r_lo, double r_hi)
+{
+    if (!m || !(tr_lo <= tr_hi) || !(r_lo <= r_hi)) return fail(EVLBM_EINVAL, "need a network and lo <= hi");
+    m->hull[0] = tr_lo;
+    m->hull[1] = tr_hi;
+    m->hull[2] = r_lo;
+    m->hull[3] = r_hi;
+    return EVLBM_OK;
+}
+
+int evlbm_mlp_get_hull(evlbm_mlp_t m, double out[4])
+{
+    if (!m || !out) return fail(EVLBM_EINVAL, "null argument");
+    for (int k = 0; k < 4; ++k) out[k] = m->hull[k];
     return EVLBM_OK;
 }
 
@@ -484,7 +510,8 @@ int evlbm_init_droplet(evlbm_t h, double cx, double cy, double cz, double R, dou
     if (rc) return rc;
     const double rl = co[0], rv = co[1], rho_c = 1.0 / (3.0 * h->b);
     bool mlp_ok = false;
-    if (profile == EVLBM_PROFILE_MLP && Tr >= 0.65 && Tr <= 0.97 && R >= 12.0 && R <= 90.0) {
+    if (profile == EVLBM_PROFILE_MLP && Tr >= mlp->hull[0] && Tr <= mlp->hull[1] && R >= mlp->hull[2] &&
+        R <= mlp->hull[3]) {
         // radial probe r/R in [0, 3]: finite, non-increasing (to 1e-3 rho_c) and
         // within [0.5 rho_v, 1.2 rho_l]
         const int np = 256;

@@ -106,3 +106,27 @@ def test_learned_warm_start_reduces_steps():
     assert r["mlp_used"]
     assert r["err0_mlp_matched"] < r["err0_tanh"] / 3
     assert r["steps_mlp_matched"] is not None and r["steps_mlp_matched"] < r["steps_tanh"]
+
+
+def test_network_is_trusted_only_on_its_training_box():
+    """A new network has an empty (T/Tc, R) box, so droplets fall back to the
+    tanh profile; training grows the box to the inputs' bounds; droplets
+    outside it fall back too."""
+    net = ev.MLP(synth.xavier_params())
+    assert net.hull()[0] > net.hull()[1]
+    L = ev.Lattice(2, 64, 48, 1, storage="f32")
+    L.set_params(**synth.params())
+    assert not L.init_droplet(14.0, 0.8, profile="mlp", mlp=net)
+    rng = np.random.default_rng(synth.SEED + 9)
+    X = np.stack([rng.uniform(0.72, 0.88, 64), rng.uniform(10.0, 22.0, 64), rng.uniform(0.0, 3.0, 64)], 1)
+    Y = rng.uniform(0.2, 1.9, 64)
+    net.train(X, Y, iters=2, lr=1e-3)
+    lo_t, hi_t, lo_r, hi_r = net.hull()
+    assert np.isclose(lo_t, np.float32(X[:, 0].min())) and np.isclose(hi_t, np.float32(X[:, 0].max()))
+    assert np.isclose(lo_r, np.float32(X[:, 1].min())) and np.isclose(hi_r, np.float32(X[:, 1].max()))
+    for R, Tr in ((30.0, 0.8), (14.0, 0.6), (14.0, 0.95)):
+        assert not L.init_droplet(R, Tr, profile="mlp", mlp=net)
+    net.set_hull(0.65, 0.97, 12.0, 90.0)
+    assert net.hull() == (0.65, 0.97, 12.0, 90.0)
+    with pytest.raises(ev.EvlbmError):
+        net.set_hull(0.9, 0.8, 12.0, 90.0)

@@ -118,6 +118,28 @@ def test_3d_droplet_ragged(storage, tol):
     _compare(g, o, tol, f"3d {storage} step 60")
 
 
+def test_3d_droplet_1000_steps():
+    """D3Q27 droplet on a 32 x 24 x 20 lattice (ragged tiles in x and y, one
+    z-chunk short of 32), R = 6, T/Tc = 0.8: moments after 1000 steps of the
+    one-pass step against the oracle, FP64 within 1e-10 and FP32 within 1e-5."""
+    shape = (20, 24, 32)
+    rho, T = _state("droplet", shape, 0.8, 1e-4)
+    o = oracle.Lattice(3, 32, 24, 20)
+    o.set_params(**P)
+    o.init(rho, T)
+    o.step(1000)
+    ro, uo, To, _ = o.moments()
+    for storage, tol in (("f64", 1e-10), ("f32", 1e-5)):
+        g = ev.Lattice(3, 32, 24, 20, storage=storage)
+        g.set_params(**P)
+        g.init_fields(rho, T)
+        g.step(1000)
+        rg, ug, Tg = g.moments()
+        e = _errs((rg, ug, Tg), (ro, uo, To))
+        print(f"3d droplet {storage} step 1000: e_rho={e[0]:.3e} e_u={e[1]:.3e} e_T={e[2]:.3e}", flush=True)
+        assert max(e) < tol, (storage, e)
+
+
 def test_2d_droplet_ragged_f32():
     shape = (1, 53, 90)
     rho, T = _state("droplet", shape, 0.7, 1e-4)
