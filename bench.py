@@ -137,6 +137,7 @@ def main():
     shape = (n, n, n)
     cells = n ** 3
     L = make_droplet(ev, synth, shape, 40.0 * n / 256, 0.8, "f32")
+    mass0 = L.global_sums()[0]
     L.step(args.warmup)
     L.synchronize()
     dt = timed_steps(L, args.steps)
@@ -180,17 +181,25 @@ def main():
                      "step_effective_GBps": round(step_eff, 1),
                      "copy_probe_GBps": round(copy_gbs, 1)},
         "mass": sums[0],
+        "mass_rel_drift": (sums[0] - mass0) / mass0,
     }
     del L
     torch.cuda.empty_cache()
 
     if not args.no_extras:
         extras = {}
-        # 2D droplet workload (512^2, FP32)
+        # 2D droplet workload (512^2, FP32, R = 40, T/Tc = 0.8), then on to
+        # 2e4 steps: spurious currents (max |u|) and the Laplace pressure jump
         L2 = make_droplet(ev, synth, (1, 512, 512), 40.0, 0.8, "f32")
         L2.step(64)
         t = timed_steps(L2, 2048, sums_every=1024)
         extras["d2q9_512sq_f32_MLUPS"] = round(512 * 512 * 2048 / t / 1e6, 1)
+        L2.step(20000 - 64 - 2048)
+        s2 = L2.global_sums()
+        md = L2.measure_droplet((255.5, 255.5), 20.0, 60.0)
+        extras["d2q9_512sq_R40_Tr08_at_2e4_steps"] = {
+            "max_u": s2[6], "dp": md[4] - md[5], "R_e": md[6], "dp_times_R_e": (md[4] - md[5]) * md[6],
+            "T_liquid_over_Tc": md[2] / synth.T_CRIT, "T_vapour_over_Tc": md[3] / synth.T_CRIT}
         del L2
         # batched sweep: 64 uneven D2Q9 domains (64^2 .. 512^2), T/Tc in [0.65, 0.97], FP32
         table = synth.batch_table()

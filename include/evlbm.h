@@ -122,7 +122,8 @@ int evlbm_step_count(evlbm_t h, int64_t *out);
  * NULL).  Errors: ESTATE, EINVAL, EHIP. */
 int evlbm_read_moments(evlbm_t h, void *rho, void *u, void *T, int where);
 
-/* FP64 global sums of the current state: out[0] = sum rho, out[1..3] =
+/* FP64 global sums of the current state: out[0] = sum rho (every cell's
+ * decoded pulled populations summed in FP64: the stored mass), out[1..3] =
  * sum rho u, out[4] = sum rho E, out[5] = sum [rho E - a rho^2 +
  * (kappa/2)|grad rho|^2], out[6] = max |u|, out[7] = min of the streamed f.
  * Blocks.  Errors: ESTATE, EHIP. */

@@ -1289,12 +1289,17 @@ __global__ void __launch_bounds__(256) k_sums(const StoreT<S> *__restrict__ pop,
         const int xs[3] = {x + 1 == p.nx ? 0 : x + 1, x, x == 0 ? p.nx - 1 : x - 1};
         const int ys[3] = {y + 1 == p.ny ? 0 : y + 1, y, y == 0 ? p.ny - 1 : y - 1};
         const int zs[3] = {z + 1 == p.nz ? 0 : z + 1, z, z == 0 ? p.nz - 1 : z - 1};
-        double fmin_ = 1e300;
+        // rho of the cell summed in FP64 over its decoded pulled populations:
+        // the global sum is then the stored mass itself, free of the moment
+        // field's per-cell rounding
+        double fmin_ = 1e300, mass = 0.0;
         for (int i = 0; i < Q; ++i) {
             const long src = (long)xs[cx_of(i) + 1] + (long)p.nx * ((long)ys[cy_of(i) + 1] + (long)p.ny * zs[cz_d<D>(i) + 1]);
             const double f = Codec<S>::dec(pop[(long)i * p.ds + src], ref_at<D, S>(p, i, src));
             fmin_ = fmin(fmin_, f);
+            mass += f;
         }
+        v[0] = mass;
         v[7] = fmin_;
     }
     block_reduce_store<8>(v, ops, partial);
