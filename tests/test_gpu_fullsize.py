@@ -21,7 +21,7 @@ def _cells(count, seed):
     c = N // 2
     special = [
         (0, 0, 0), (N - 1, N - 1, N - 1),            # periodic corners
-        (63, 3, 31), (64, 4, 32), (127, 7, 63),       # 64 x 4 column and 32-plane chunk edges
+        (63, 3, 39), (64, 4, 40), (127, 7, 79),       # 64 x 4 column and 40-plane chunk edges
         (0, N - 1, 128), (N - 1, 0, 224),
         (c + 40, c, c), (c, c + 39, c), (c, c, c - 41),  # on the droplet's interface
         (c, c, c),                                     # liquid
