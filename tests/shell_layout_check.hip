@@ -1,0 +1,45 @@
+// Host check of the shell slot layout of the pushed moments (the library's
+// own Shell<TX, TY, ZC>): for every tile chunk extent W <= TX, H <= TY,
+// Zc <= ZC, the targets a chunk writes to its shell (the tile + 1 ring of each
+// of its planes, the whole tile + 1 face below and above) get distinct slots
+// inside [0, SIZE).  Built and run by test_shell_layout.py; exit status 0 on
+// success.
+#include <cstdio>
+#include <vector>
+
+#include "lbm_kernels.hpp"
+
+template <int TX, int TY, int ZC>
+static int check()
+{
+    using SH = evlbm::Shell<TX, TY, ZC>;
+    long cases = 0;
+    for (int W = 1; W <= TX; ++W)
+        for (int H = 1; H <= TY; ++H)
+            for (int Zc = 1; Zc <= ZC; ++Zc) {
+                std::vector<int> seen(SH::SIZE, 0);
+                auto put = [&](int lx, int ly, int lz) {
+                    const int s = SH::slot(lx, ly, lz, H, Zc);
+                    if (s < 0 || s >= SH::SIZE || seen[s]++) {
+                        std::printf("TX %d TY %d ZC %d: W %d H %d Zc %d target (%d, %d, %d) slot %d %s\n", TX, TY, ZC,
+                                    W, H, Zc, lx, ly, lz, s, (s < 0 || s >= SH::SIZE) ? "out of range" : "reused");
+                        return false;
+                    }
+                    return true;
+                };
+                for (int lz = -1; lz <= Zc; ++lz)
+                    for (int ly = -1; ly <= H; ++ly)
+                        for (int lx = -1; lx <= W; ++lx) {
+                            const bool inside = lx >= 0 && lx < W && ly >= 0 && ly < H && lz >= 0 && lz < Zc;
+                            if (!inside && !put(lx, ly, lz)) return 1;
+                        }
+                ++cases;
+            }
+    std::printf("Shell<%d, %d, %d>: %ld chunk extents, slots distinct and in range\n", TX, TY, ZC, cases);
+    return 0;
+}
+
+int main()
+{
+    return check<64, 4, 40>() | check<16, 8, 40>() | check<64, 4, 32>();
+}
