@@ -615,16 +615,20 @@ __global__ void __launch_bounds__(TX *TY)
     // bytes per moment array; with buffer addressing (27 ds sizeof(T) < 2^32)
     // all five arrays of m lie within 32-bit byte offsets of its base
     const unsigned NB = (unsigned)p.N * RS;
-    __shared__ R s_rho[ZT::NRHO][ZT::N3];
+    // rho ring: with PUSH a barrier ends every iteration, so the slot of plane
+    // k-1 is free when iteration k writes plane k+3 (4 planes); without it a
+    // fast wave may write k+4 while a slow one still reads k (5 planes)
+    constexpr int NRHO = PUSH ? 4 : ZT::NRHO;
+    __shared__ R s_rho[NRHO][ZT::N3];
     __shared__ R s_lap[ZT::NLAP][ZT::N2];
     __shared__ R s_fld[ZT::NFLD][ZT::NF][ZT::N1];
     // PUSH: in-row sums (Pf = sum f, Jx = sum c_x f, Pg = sum g) per c_z handed
     // to the row above (c_y = +1) and below (c_y = -1); the two end lanes'
     // values leaving the row in x; the ring targets' sums for 3 planes
     using SH = Shell<TX, TY, ZC>;
-    constexpr int NXR = PUSH ? (TY > 1 ? TY - 1 : 1) : 1;
-    __shared__ R s_xup[NXR][PUSH ? 9 : 1][PUSH ? TX : 1];
-    __shared__ R s_xdn[NXR][PUSH ? 9 : 1][PUSH ? TX : 1];
+    constexpr int NXR = PUSH ? TY : 1;
+    __shared__ R s_xup[NXR][PUSH ? 9 : 1][PUSH ? TX : 1];  // row ty's parts for row ty + 1 (c_y = +1)
+    __shared__ R s_xdn[NXR][PUSH ? 9 : 1][PUSH ? TX : 1];  // row ty's parts for row ty - 1 (c_y = -1)
     __shared__ R s_edge[2][PUSH ? TY : 1][PUSH ? 9 : 1][2];
     __shared__ R s_ring[PUSH ? 3 : 1][PUSH ? 5 : 1][PUSH ? SH::RING : 1];
 
@@ -710,7 +714,7 @@ __global__ void __launch_bounds__(TX *TY)
     // plane k+2 on tile + 2, force and half-step fields of plane k+1 on tile + 1
     auto stencil_stages = [&](int k, auto &&after_first_barrier) {
         {
-            R *dstp = s_rho[ring_slot(k + 3, ZT::NRHO)];
+            R *dstp = s_rho[ring_slot(k + 3, NRHO)];
 #pragma unroll
             for (int j = 0; j < NR3; ++j)
                 if (tid + j * ZT::NT < ZT::N3) dstp[tid + j * ZT::NT] = rv[j];
@@ -718,8 +722,8 @@ __global__ void __launch_bounds__(TX *TY)
         __syncthreads();
         after_first_barrier();
         {
-            const R *a = s_rho[ring_slot(k + 1, ZT::NRHO)], *b = s_rho[ring_slot(k + 2, ZT::NRHO)],
-                    *c = s_rho[ring_slot(k + 3, ZT::NRHO)];
+            const R *a = s_rho[ring_slot(k + 1, NRHO)], *b = s_rho[ring_slot(k + 2, NRHO)],
+                    *c = s_rho[ring_slot(k + 3, NRHO)];
             R *dstp = s_lap[ring_slot(k + 2, ZT::NLAP)];
             for (int t = tid; t < ZT::N2; t += ZT::NT) {
                 const int lx = t % ZT::R2X, ly = t / ZT::R2X;
@@ -728,8 +732,8 @@ __global__ void __launch_bounds__(TX *TY)
         }
         __syncthreads();
         {
-            const R *ra = s_rho[ring_slot(k, ZT::NRHO)], *rb = s_rho[ring_slot(k + 1, ZT::NRHO)],
-                    *rc = s_rho[ring_slot(k + 2, ZT::NRHO)];
+            const R *ra = s_rho[ring_slot(k, NRHO)], *rb = s_rho[ring_slot(k + 1, NRHO)],
+                    *rc = s_rho[ring_slot(k + 2, NRHO)];
             const R *la = s_lap[ring_slot(k, ZT::NLAP)], *lb = s_lap[ring_slot(k + 1, ZT::NLAP)],
                     *lc = s_lap[ring_slot(k + 2, ZT::NLAP)];
             R(*fd)[ZT::N1] = s_fld[ring_slot(k + 1, ZT::NFLD)];
@@ -788,16 +792,24 @@ __global__ void __launch_bounds__(TX *TY)
 
     // PUSH state: the decoded stored values of this cell's collision (zero on
     // lanes past a ragged edge), this thread's own target sums for planes
-    // k-1, k, k+1 (rho, jx, jy, jz, e), and the ring targets it owns:
-    // bottom row (tx, -1) if ty == 0, top row (tx, H) if ty == H - 1, and the
-    // column targets (-1 or W, c % (H + 2) - 1) on c = tid - TX < 2 (H + 2)
-    // (threads of the second row, which own no ring row when TY > 2).
+    // k-1, k, k+1 (rho, jx, jy, jz, e), and the ring targets it owns: the
+    // bottom row (tx, -1), the top row (tx, H) and the column targets (-1 or
+    // W, c % (H + 2) - 1) on c = tid - TX * TY_COL < 2 (H + 2).  With one row
+    // per wave (SPREAD) every row hands both cross-row parts to LDS and the
+    // three ring jobs run after the hand-over barrier on waves 1, 2 and 3, so
+    // that no wave carries two of them; with several rows per wave the first
+    // and last rows commit the ring rows before the barrier from registers
+    // (measured faster for the 16 x 8 tile of two waves).
     R vf[Q], vg[Q], acc[3][5];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc[j][q] = R(0);
-    const int col_c = tid - (TY > 2 ? TX : 0);
+    constexpr bool SPREAD = TX >= 64;
+    constexpr int TY_COL = SPREAD ? 3 % TY : (TY > 2 ? 1 : 0);
+    static_assert(!PUSH || TX * (TY - TY_COL) >= 2 * (TY + 2), "the column owners must fit in the tile");
+    const int ty_bot = SPREAD ? 1 % TY : 0, ty_top = SPREAD ? 2 % TY : H - 1;
+    const int col_c = tid - TX * TY_COL;
     const bool col_owner = col_c >= 0 && col_c < 2 * (H + 2);
     const int col_side = col_c >= H + 2 ? 1 : 0, col_ly = col_c - col_side * (H + 2) - 1;
     const int col_lx = col_side ? W : -1;
@@ -864,7 +876,7 @@ __global__ void __launch_bounds__(TX *TY)
     // push the collided plane k: in-row shifts and sums, the row's own part
     // into acc, the parts for the rows above and below into LDS
     auto push_plane = [&](int k) {
-        R rc_dn[3][5], rc_up[3][5];  // parts for the rows below (c_y = -1) and above (c_y = +1) the tile
+        R rc_dn[3][5], rc_up[3][5];  // without SPREAD: parts for the ring rows below and above the tile
 #pragma unroll
         for (int cz = -1; cz <= 1; ++cz)
 #pragma unroll
@@ -890,32 +902,37 @@ __global__ void __launch_bounds__(TX *TY)
                     if (cz != 0) acc[cz + 1][3] += cz > 0 ? Pf : -Pf;
                     acc[cz + 1][4] += Pg;
                 } else if (cy == 1) {
-                    if (ty < H - 1) {
+                    if (SPREAD ? ty < H : ty < H - 1) {
                         s_xup[ty][3 * (cz + 1)][tx] = Pf;
                         s_xup[ty][3 * (cz + 1) + 1][tx] = Jx;
                         s_xup[ty][3 * (cz + 1) + 2][tx] = Pg;
                     }
-                    rc_up[cz + 1][0] = Pf;
-                    rc_up[cz + 1][1] = Jx;
-                    rc_up[cz + 1][2] = Pf;
-                    rc_up[cz + 1][3] = cz == 0 ? R(0) : cz > 0 ? Pf : -Pf;
-                    rc_up[cz + 1][4] = Pg;
-                } else {
-                    if (ty >= 1 && ty < H) {
-                        s_xdn[ty - 1][3 * (cz + 1)][tx] = Pf;
-                        s_xdn[ty - 1][3 * (cz + 1) + 1][tx] = Jx;
-                        s_xdn[ty - 1][3 * (cz + 1) + 2][tx] = Pg;
+                    if constexpr (!SPREAD) {
+                        rc_up[cz + 1][0] = Pf;
+                        rc_up[cz + 1][1] = Jx;
+                        rc_up[cz + 1][2] = Pf;
+                        rc_up[cz + 1][3] = cz == 0 ? R(0) : cz > 0 ? Pf : -Pf;
+                        rc_up[cz + 1][4] = Pg;
                     }
-                    rc_dn[cz + 1][0] = Pf;
-                    rc_dn[cz + 1][1] = Jx;
-                    rc_dn[cz + 1][2] = -Pf;
-                    rc_dn[cz + 1][3] = cz == 0 ? R(0) : cz > 0 ? Pf : -Pf;
-                    rc_dn[cz + 1][4] = Pg;
+                } else {
+                    if ((SPREAD || ty >= 1) && ty < H) {
+                        s_xdn[ty][3 * (cz + 1)][tx] = Pf;
+                        s_xdn[ty][3 * (cz + 1) + 1][tx] = Jx;
+                        s_xdn[ty][3 * (cz + 1) + 2][tx] = Pg;
+                    }
+                    if constexpr (!SPREAD) {
+                        rc_dn[cz + 1][0] = Pf;
+                        rc_dn[cz + 1][1] = Jx;
+                        rc_dn[cz + 1][2] = -Pf;
+                        rc_dn[cz + 1][3] = cz == 0 ? R(0) : cz > 0 ? Pf : -Pf;
+                        rc_dn[cz + 1][4] = Pg;
+                    }
                 }
             }
-        // the first and last rows own the ring rows below and above the tile
-        if (ty == 0 && tx < W) ring_commit(k, tx, -1, rc_dn);
-        if (ty == H - 1 && tx < W) ring_commit(k, tx, H, rc_up);
+        if constexpr (!SPREAD) {
+            if (ty == ty_bot && tx < W) ring_commit(k, tx, -1, rc_dn);
+            if (ty == ty_top && tx < W) ring_commit(k, tx, H, rc_up);
+        }
     };
     // gather the cross-row parts of source plane k (after the barrier that
     // follows its push), then plane k - 1 is complete: write it and rotate
@@ -932,14 +949,33 @@ __global__ void __launch_bounds__(TX *TY)
                     acc[cz + 1][4] += s_xup[ty - 1][3 * (cz + 1) + 2][tx];
                 }
                 if (ty + 1 < H) {  // from the row above, c_y = -1
-                    const R Pf = s_xdn[ty][3 * (cz + 1)][tx];
+                    const R Pf = s_xdn[ty + 1][3 * (cz + 1)][tx];
                     acc[cz + 1][0] += Pf;
-                    acc[cz + 1][1] += s_xdn[ty][3 * (cz + 1) + 1][tx];
+                    acc[cz + 1][1] += s_xdn[ty + 1][3 * (cz + 1) + 1][tx];
                     acc[cz + 1][2] -= Pf;
                     if (cz != 0) acc[cz + 1][3] += cz > 0 ? Pf : -Pf;
-                    acc[cz + 1][4] += s_xdn[ty][3 * (cz + 1) + 2][tx];
+                    acc[cz + 1][4] += s_xdn[ty + 1][3 * (cz + 1) + 2][tx];
                 }
             }
+        }
+        // SPREAD: the ring rows below and above the tile, from the first row's
+        // parts going down and the last row's going up
+        auto commit_row = [&](int ly, const auto &xb, R sy) {
+            R rc[3][5];
+#pragma unroll
+            for (int cz = -1; cz <= 1; ++cz) {
+                const R Pf = xb[3 * (cz + 1)][tx];
+                rc[cz + 1][0] = Pf;
+                rc[cz + 1][1] = xb[3 * (cz + 1) + 1][tx];
+                rc[cz + 1][2] = sy * Pf;
+                rc[cz + 1][3] = cz == 0 ? R(0) : cz > 0 ? Pf : -Pf;
+                rc[cz + 1][4] = xb[3 * (cz + 1) + 2][tx];
+            }
+            ring_commit(k, tx, ly, rc);
+        };
+        if constexpr (SPREAD) {
+            if (ty == ty_bot && tx < W) commit_row(-1, s_xdn[0], R(-1));
+            if (ty == ty_top && tx < W) commit_row(H, s_xup[H - 1], R(1));
         }
         if (col_owner) {  // column and corner targets: values leaving the end lanes
             R rc[3][5];
@@ -998,7 +1034,7 @@ __global__ void __launch_bounds__(TX *TY)
                 fp[q] = s_fld[ring_slot(k + 1, ZT::NFLD)][q];
             }
             const int c1 = (tx + 1) + ZT::R1X * (ty + 1);
-            const R rho = s_rho[ring_slot(k, ZT::NRHO)][(tx + 3) + ZT::R3X * (ty + 3)];
+            const R rho = s_rho[ring_slot(k, NRHO)][(tx + 3) + ZT::R3X * (ty + 3)];
             const R inv_rho = rcp(rho);
             const R K = Kc;
             const R RT = K * (R(2) / R(3));
@@ -1048,8 +1084,8 @@ __global__ void __launch_bounds__(TX *TY)
         // planes z1 - 1 (inside the chunk) and z1 (the face above)
         finish_plane(z1 - 1, acc[0]);
         finish_plane(z1, acc[1]);
-        if (ty == 0 && tx < W) ring_final(tx, -1);
-        if (ty == H - 1 && tx < W) ring_final(tx, H);
+        if (ty == ty_bot && tx < W) ring_final(tx, -1);
+        if (ty == ty_top && tx < W) ring_final(tx, H);
         if (col_owner) ring_final(col_lx, col_ly);
     }
 }
