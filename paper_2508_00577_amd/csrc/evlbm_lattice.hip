@@ -119,7 +119,7 @@ struct Ops {
             collide_zm<true>(h, src, dst);
             if (between) (void)hipEventRecord(between, h->stream);
             const int nbx = (h->nx + TX - 1) / TX, nby = (h->ny + TY - 1) / TY, nbz = (h->nz + ZC - 1) / ZC;
-            hipLaunchKernelGGL((k_push_fixup<R, TX, TY, ZC>), dim3(nbx * nby * nbz), dim3(TX, TY), 0, h->stream,
+            hipLaunchKernelGGL((k_push_fixup<R, TX, TY, ZC>), dim3(nbx * nby * nbz, ZC), dim3(TX, TY), 0, h->stream,
                                (R *)h->m_alt, (const R *)h->shell, h->nx, h->ny, h->nz, nbx, nby, nbz);
         }
     }

@@ -1096,19 +1096,21 @@ __global__ void __launch_bounds__(TX *TY)
 // before (if the cell is the chunk's first, it lies on that chunk's far side)
 // and the one after (if it is the last; on that chunk's near side); a lattice
 // one chunk wide is its own neighbour, so periodic wrap needs no special case.
-// One workgroup of TX x TY threads per tile chunk (natural order); a thread
-// owns one column of the chunk and visits its face cells.
+// One workgroup of TX x TY threads per plane of a tile chunk (blockIdx.x the
+// chunk in natural order, blockIdx.y the plane), a thread per cell: the cells
+// of a chunk's planes are independent, so no wave walks the chunk's planes
+// one after another.
 template <typename R, int TX, int TY, int ZC>
 __global__ void __launch_bounds__(TX *TY) k_push_fixup(R *__restrict__ m, const R *__restrict__ shell, int nx, int ny,
                                                        int nz, int nbx, int nby, int nbz)
 {
     using SH = Shell<TX, TY, ZC>;
-    const int tile = blockIdx.x;
+    const int tile = blockIdx.x, lz = blockIdx.y;
     const int bx = tile % nbx, by = (tile / nbx) % nby, bz = tile / (nbx * nby);
     const int x0 = bx * TX, y0 = by * TY, z0 = bz * ZC;
     const int W = min(TX, nx - x0), H = min(TY, ny - y0), Zc = min(ZC, nz - z0);
     const int tx = threadIdx.x, ty = threadIdx.y;
-    if (tx >= W || ty >= H) return;
+    if (tx >= W || ty >= H || lz >= Zc) return;
     const unsigned N = (unsigned)nx * (unsigned)ny * (unsigned)nz;
     // candidates per axis: tile index offset and the cell's local coordinate in that tile
     int nxc = 1, nyc = 1, txi[3] = {bx, 0, 0}, lxs[3] = {tx, 0, 0}, tyi[3] = {by, 0, 0}, lys[3] = {ty, 0, 0};
@@ -1130,40 +1132,36 @@ __global__ void __launch_bounds__(TX *TY) k_push_fixup(R *__restrict__ m, const 
         tyi[nyc] = by == nby - 1 ? 0 : by + 1;
         lys[nyc++] = -1;
     }
-    const bool side = nxc > 1 || nyc > 1;  // on an x or y face: every plane
-    const int bzm = bz == 0 ? nbz - 1 : bz - 1, bzp = bz == nbz - 1 ? 0 : bz + 1;
-    const int Zcm = min(ZC, nz - bzm * ZC);
-    for (int lz = 0; lz < Zc; lz = (side || lz == Zc - 1) ? lz + 1 : Zc - 1) {
-        int nzc = 1, tzi[3] = {bz, 0, 0}, lzs[3] = {lz, 0, 0};
-        if (lz == 0) {
-            tzi[nzc] = bzm;
-            lzs[nzc++] = Zcm;
-        }
-        if (lz == Zc - 1) {
-            tzi[nzc] = bzp;
-            lzs[nzc++] = -1;
-        }
-        if (nzc == 1 && !side) continue;
-        const unsigned cell = (unsigned)(x0 + tx) + (unsigned)nx * ((unsigned)(y0 + ty) + (unsigned)ny * (unsigned)(z0 + lz));
-        R sum[5];
+    int nzc = 1, tzi[3] = {bz, 0, 0}, lzs[3] = {lz, 0, 0};
+    if (lz == 0) {
+        const int bzm = bz == 0 ? nbz - 1 : bz - 1;
+        tzi[nzc] = bzm;
+        lzs[nzc++] = min(ZC, nz - bzm * ZC);
+    }
+    if (lz == Zc - 1) {
+        tzi[nzc] = bz == nbz - 1 ? 0 : bz + 1;
+        lzs[nzc++] = -1;
+    }
+    if (nzc == 1 && nxc == 1 && nyc == 1) return;  // inside the chunk: complete already
+    const unsigned cell = (unsigned)(x0 + tx) + (unsigned)nx * ((unsigned)(y0 + ty) + (unsigned)ny * (unsigned)(z0 + lz));
+    R sum[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) sum[q] = m[q * (size_t)N + cell];
-        for (int kz = 0; kz < nzc; ++kz) {
-            const int Zc2 = min(ZC, nz - tzi[kz] * ZC);
-            for (int ky = 0; ky < nyc; ++ky) {
-                const int H2 = min(TY, ny - tyi[ky] * TY);
-                for (int kx = 0; kx < nxc; ++kx) {
-                    if (kx == 0 && ky == 0 && kz == 0) continue;
-                    const R *sh = shell + (size_t)(txi[kx] + nbx * (tyi[ky] + nby * tzi[kz])) * 5 * SH::SIZE +
-                                  SH::slot(lxs[kx], lys[ky], lzs[kz], H2, Zc2);
+    for (int q = 0; q < 5; ++q) sum[q] = m[q * (size_t)N + cell];
+    for (int kz = 0; kz < nzc; ++kz) {
+        const int Zc2 = min(ZC, nz - tzi[kz] * ZC);
+        for (int ky = 0; ky < nyc; ++ky) {
+            const int H2 = min(TY, ny - tyi[ky] * TY);
+            for (int kx = 0; kx < nxc; ++kx) {
+                if (kx == 0 && ky == 0 && kz == 0) continue;
+                const R *sh = shell + (size_t)(txi[kx] + nbx * (tyi[ky] + nby * tzi[kz])) * 5 * SH::SIZE +
+                              SH::slot(lxs[kx], lys[ky], lzs[kz], H2, Zc2);
 #pragma unroll
-                    for (int q = 0; q < 5; ++q) sum[q] += sh[q * SH::SIZE];
-                }
+                for (int q = 0; q < 5; ++q) sum[q] += sh[q * SH::SIZE];
             }
         }
-#pragma unroll
-        for (int q = 0; q < 5; ++q) m[q * (size_t)N + cell] = sum[q];
     }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) m[q * (size_t)N + cell] = sum[q];
 }
 
 // ------------------------------------------------------------ readout
