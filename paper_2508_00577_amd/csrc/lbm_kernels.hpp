@@ -263,6 +263,12 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
         const StoreT<S> gq = Codec<S>::enc(gn, rg);
         pops.st(i, cell, fq);
         pops.st(Q + i, cell, gq);
+        // FP32 and FP64 storage: keep the stores here.  The scheduler
+        // otherwise sinks all 2Q of them to the end, and the next plane's
+        // loads, which reuse their source registers, must then wait for every
+        // one of them to retire.  (With 16-bit storage the pinned order
+        // measured slower.)
+        if constexpr (sizeof(StoreT<S>) >= 4) __builtin_amdgcn_sched_barrier(0);
         const R fd = Codec<S>::dec(fq, rf), gd = Codec<S>::dec(gq, rg);
         sf += (double)fd;
         sg += (double)gd;
