@@ -83,8 +83,9 @@ struct Ops {
     // lines, so the pulled rows of the 18 directions with cx != 0 touch three)
     static constexpr int TX = (S == EVLBM_F64) ? 16 : 64;
     static constexpr int TY = (S == EVLBM_F64) ? 8 : 4;
-    // (40 planes per chunk measured best of 32..64 at 256^3: 2.9 % faster than 32)
-    static constexpr int ZC = 40;
+    // planes per chunk, measured at 256^3: in FP32 40 is best of 32..64 (2.9 %
+    // faster than 32); the FP64 tile (one wave per SIMD) gains up to 64
+    static constexpr int ZC = (S == EVLBM_F64) ? 64 : 40;
     // the one-pass step (FP32 and FP64 storage: with 16-bit storage the
     // collision's registers leave no room for the pushed sums at 2 waves per SIMD)
     static constexpr bool PUSH_OK = D == 3 && (S == EVLBM_F32 || S == EVLBM_F64);

@@ -41,5 +41,5 @@ static int check()
 
 int main()
 {
-    return check<64, 4, 40>() | check<16, 8, 40>() | check<64, 4, 32>();
+    return check<64, 4, 40>() | check<16, 8, 64>() | check<16, 8, 40>() | check<64, 4, 32>();
 }
