@@ -54,6 +54,23 @@ def test_batch_domain_equals_single_lattice_bitwise(storage, steps):
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb), f"domain {k}"
 
 
+def test_batch_graph_replays_match_eager_steps():
+    """Steps replayed from the captured 32-step graph (a call of 64 steps: two
+    replays) give the same bits as the same steps launched eagerly (calls of
+    16 steps, below the graph chunk); every block is compared after a
+    read-back, i.e. with eager work and synchronisation between replays."""
+    a, _ = _batch("f32", 0)
+    e, _ = _batch("f32", 0)
+    for r in range(3):
+        a.step(64)
+        for _ in range(4):
+            e.step(16)
+        for k in range(len(DOMS)):
+            fa, ga = a.get_populations(k)
+            fe, ge = e.get_populations(k)
+            assert np.array_equal(fa, fe) and np.array_equal(ga, ge), f"block {r}, domain {k}"
+
+
 def test_batch_tile_shapes_agree():
     res = []
     for v in range(4):

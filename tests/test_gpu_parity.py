@@ -217,13 +217,15 @@ def test_graph_replay_matches_eager():
         L.set_params(**P)
         L.init_fields(rho, T)
     b.set_option(ev.OPT_USE_GRAPH, 0)
-    for n in (70, 5, 64, 33):
+    # every call replays the captured chunks again; the read-back between
+    # calls is eager work with synchronisation, and each state is compared
+    for n in (70, 5, 64, 33, 64):
         a.step(n)
         b.step(n)
-    fa, ga = a.get_populations()
-    fb, gb = b.get_populations()
-    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
-    assert a.step_count == b.step_count == 172
+        fa, ga = a.get_populations()
+        fb, gb = b.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), f"after a call of {n} steps"
+    assert a.step_count == b.step_count == 236
 
 
 @pytest.mark.parametrize("shape,steps", [((70, 12, 20), 20), ((1, 9, 17), 30), ((2, 5, 6), 30)])

@@ -85,12 +85,14 @@ def test_one_pass_graph_replay_matches_eager():
     rho, T = _state(shape)
     a = _lattice(shape, "f32", True, rho, T, graph=True)
     b = _lattice(shape, "f32", True, rho, T, graph=False)
-    for n in (70, 5, 64, 33):
+    for n in (70, 5, 64, 33, 64):
         a.step(n)
         b.step(n)
-    fa, ga = a.get_populations()
-    fb, gb = b.get_populations()
-    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+        fa, ga = a.get_populations()
+        fb, gb = b.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), f"after a call of {n} steps"
+        ma, mb = a.moments(), b.moments()
+        assert all(np.array_equal(x, y) for x, y in zip(ma, mb)), f"moments after a call of {n} steps"
 
 
 @pytest.mark.parametrize("storage", ["f32", "f64"])
