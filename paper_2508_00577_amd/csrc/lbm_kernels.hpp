@@ -543,15 +543,21 @@ __device__ inline int xcd_tile(int b, int T)
 // that sum coming from its own cells.  Targets inside the chunk receive it in
 // the moment field directly; the targets around it (tile + 1 in x, y and z)
 // receive it in the chunk's shell of partial sums, which a fix-up pass adds
-// to the owners of those cells.  Shell slots of one moment:
-//   plane lz in [0, Zc): the tile + 1 ring, RING slots (rows ly = -1 and
-//     ly = H with lx in [-1, W], then columns lx = -1 and lx = W)
+// to the owners of those cells.  Shell slots of one moment (SIZE, a multiple
+// of 32 values, so that every moment and chunk starts on a 128-byte line):
+//   plane lz in [0, Zc), PLANE slots (a multiple of 32): the rows ly = -1 and
+//     ly = H with lx in [0, W) (each starts on a line when TX is a multiple
+//     of 32), then the columns and corners lx = -1 and lx = W with ly in
+//     [-1, H] (together on one line for a 64 x 4 tile)
 //   planes lz = -1 and lz = Zc: the whole tile + 1 face, FACE slots each.
+// In LDS the collision keeps a plane's ring targets at ring(lx, ly, H), RING
+// slots: rows with their corners, then columns.
 template <int TX, int TY, int ZC>
 struct Shell {
     static constexpr int RING = 2 * (TX + 2) + 2 * TY;
+    static constexpr int PLANE = (2 * TX + 2 * (TY + 2) + 31) / 32 * 32;
     static constexpr int FACE = (TX + 2) * (TY + 2);
-    static constexpr int SIZE = ZC * RING + 2 * FACE;
+    static constexpr int SIZE = (ZC * PLANE + 2 * FACE + 31) / 32 * 32;
     __host__ __device__ static int ring(int lx, int ly, int H)
     {
         if (ly < 0) return lx + 1;
@@ -559,11 +565,12 @@ struct Shell {
         return 2 * (TX + 2) + (lx < 0 ? ly : TY + ly);
     }
     __host__ __device__ static int face(int lx, int ly) { return (lx + 1) + (TX + 2) * (ly + 1); }
-    __host__ __device__ static int slot(int lx, int ly, int lz, int H, int Zc)
+    __host__ __device__ static int slot(int lx, int ly, int lz, int W, int H, int Zc)
     {
-        if (lz < 0) return ZC * RING + face(lx, ly);
-        if (lz >= Zc) return ZC * RING + FACE + face(lx, ly);
-        return lz * RING + ring(lx, ly, H);
+        if (lz < 0) return ZC * PLANE + face(lx, ly);
+        if (lz >= Zc) return ZC * PLANE + FACE + face(lx, ly);
+        if (lx < 0 || lx >= W) return lz * PLANE + 2 * TX + (lx < 0 ? 0 : TY + 2) + ly + 1;
+        return lz * PLANE + (ly < 0 ? 0 : TX) + lx;
     }
 };
 
@@ -838,7 +845,7 @@ __global__ void __launch_bounds__(TX *TY)
             a1[q] = r1[q * SH::RING];
             a2[q] = r2[q * SH::RING];
         }
-        const int sl = SH::slot(lx, ly, kk - 1 - z0, H, Zc);
+        const int sl = SH::slot(lx, ly, kk - 1 - z0, W, H, Zc);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
             r0[q * SH::RING] = R(0);
@@ -853,7 +860,7 @@ __global__ void __launch_bounds__(TX *TY)
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
             const int kk = z1 - 1 + d;
-            const int sl = SH::slot(lx, ly, kk - z0, H, Zc);
+            const int sl = SH::slot(lx, ly, kk - z0, W, H, Zc);
 #pragma unroll
             for (int q = 0; q < 5; ++q)
                 st_at(shell_t, (unsigned)(q * SH::SIZE + sl) * RS, s_ring[ring_slot(kk, 3)][q][ri]);
@@ -873,7 +880,7 @@ __global__ void __launch_bounds__(TX *TY)
                         st_at(m_next + q * N, c, a[q]);
                 }
             } else {
-                const int sl = SH::slot(tx, ty, lz, H, Zc);
+                const int sl = SH::slot(tx, ty, lz, W, H, Zc);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) st_at(shell_t, (unsigned)(q * SH::SIZE + sl) * RS, a[q]);
             }
@@ -1173,8 +1180,9 @@ __global__ void __launch_bounds__(TX *TY) k_push_fixup(R *__restrict__ m, const 
             const int H2 = min(TY, ny - tyi[ky] * TY);
             for (int kx = 0; kx < nxc; ++kx) {
                 if (kx == 0 && ky == 0 && kz == 0) continue;
+                const int W2 = min(TX, nx - txi[kx] * TX);
                 const R *sh = shell + (size_t)(txi[kx] + nbx * (tyi[ky] + nby * tzi[kz])) * 5 * SH::SIZE +
-                              SH::slot(lxs[kx], lys[ky], lzs[kz], H2, Zc2);
+                              SH::slot(lxs[kx], lys[ky], lzs[kz], W2, H2, Zc2);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) sum[q] += sh[q * SH::SIZE];
             }

@@ -13,13 +13,22 @@ template <int TX, int TY, int ZC>
 static int check()
 {
     using SH = evlbm::Shell<TX, TY, ZC>;
+    // every moment and chunk starts on a 128-byte line (32 FP32 values), and
+    // so does every ring row of a 32- or 64-wide tile
+    for (int lz = 0; lz < ZC; ++lz)
+        if (SH::SIZE % 32 != 0 ||
+            (TX % 32 == 0 && (SH::slot(0, -1, lz, TX, TY, ZC) % 32 != 0 || SH::slot(0, TY, lz, TX, TY, ZC) % 32 != 0))) {
+            std::printf("TX %d TY %d ZC %d: SIZE %d or a ring row of plane %d is not line-aligned\n", TX, TY, ZC,
+                        SH::SIZE, lz);
+            return 1;
+        }
     long cases = 0;
     for (int W = 1; W <= TX; ++W)
         for (int H = 1; H <= TY; ++H)
             for (int Zc = 1; Zc <= ZC; ++Zc) {
                 std::vector<int> seen(SH::SIZE, 0);
                 auto put = [&](int lx, int ly, int lz) {
-                    const int s = SH::slot(lx, ly, lz, H, Zc);
+                    const int s = SH::slot(lx, ly, lz, W, H, Zc);
                     if (s < 0 || s >= SH::SIZE || seen[s]++) {
                         std::printf("TX %d TY %d ZC %d: W %d H %d Zc %d target (%d, %d, %d) slot %d %s\n", TX, TY, ZC,
                                     W, H, Zc, lx, ly, lz, s, (s < 0 || s >= SH::SIZE) ? "out of range" : "reused");
