@@ -61,9 +61,11 @@ enum {
     EVLBM_OPT_CHECK_EVERY = 4, /* scan for non-finite densities every K steps (0 = never) */
     EVLBM_OPT_USE_GRAPH = 5,   /* 1: replay step chunks from a captured hipGraph (default 1) */
     EVLBM_OPT_REREF_EVERY = 6, /* 16-bit storage: re-reference every K steps (0 = never; default 100) */
-    EVLBM_OPT_PUSH_MOMENTS = 7 /* D3Q27 with FP32 or FP64 storage: 1 = one-pass step, the collision pushes
-                                  the next moments (default 1); 0 = two-pass step, the moments are pulled
-                                  again before each collision (always so for D2Q9 and 16-bit storage) */
+    EVLBM_OPT_PUSH_MOMENTS = 7 /* 1 = one-pass step (default), 0 = two-pass step, where the moments are pulled
+                                  again before each collision.  D3Q27 with FP32 or FP64 storage: the collision
+                                  pushes the next moments (16-bit D3Q27 storage is always two-pass).  D2Q9:
+                                  the collision sums its tile's halo moments from the pulled populations;
+                                  the result is bit for bit the two-pass step's */
 };
 
 enum { EVLBM_MEASURE_SLAB = 1, EVLBM_MEASURE_DROPLET = 2 };
@@ -164,7 +166,7 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path);
  * average durations in milliseconds: out[1] = stencil + collision kernel,
  * out[0] = the other kernel of the step: the pulled-moment kernel of the
  * two-pass step, or the fix-up of the pushed moments of the one-pass D3Q27
- * step (EVLBM_OPT_PUSH_MOMENTS).  Blocks.
+ * step (EVLBM_OPT_PUSH_MOMENTS); 0 for the one-pass D2Q9 step.  Blocks.
  * Errors: EINVAL (nsteps outside 1..4096), ESTATE, EHIP. */
 int evlbm_profile_step(evlbm_t h, int nsteps, double out[2]);
 

@@ -1,8 +1,9 @@
 // Batched D2Q9 domains of uneven sizes (a temperature or size sweep) advanced
 // together: one population arena, a device table of domains and a list of
 // BX x BY tiles covering all of them; each step is one persistent launch of
-// the moment kernel and one of the stencil + collision kernel, whose
-// workgroups stride over the whole tile list.  Step chunks are replayed from
+// the stencil + collision kernel, whose workgroups stride over the whole tile
+// list and sum each tile's halo moments from the pulled populations (the
+// moment kernel runs only for readouts).  Step chunks are replayed from
 // captured hipGraphs.  The tile shape is chosen by an autotuner among the
 // compiled shapes.  Every cell runs the same device code as a single lattice,
 // so a domain of the batch evolves bit for bit as the same domain alone with
@@ -29,10 +30,10 @@ struct DomainRec {
     long cell_off;  // cells before this domain (reference-density arena)
 };
 
-// Compiled tile shapes: (BX, BY)
+// Compiled tile shapes: (BX, BY); variant 1 is a single lattice's D2Q9 tile
 static constexpr int NVARIANT = 4;
-static constexpr int VBX[NVARIANT] = {64, 32, 128, 64};
-static constexpr int VBY[NVARIANT] = {4, 8, 2, 8};
+static constexpr int VBX[NVARIANT] = {64, 64, 128, 64};
+static constexpr int VBY[NVARIANT] = {4, 16, 2, 8};
 
 template <typename R>
 __device__ inline StepParams<R> domain_params(const StepParams<R> &p, const DomainRec &d)
@@ -71,7 +72,7 @@ __global__ void __launch_bounds__(BX *BY)
         const int4 tl = tiles[t];
         const DomainRec d = dom[tl.x];
         const StepParams<RealT<S>> q = domain_params(p, d);
-        collide_block<2, S, BX, BY, 1>(src + d.pop_off, dst + d.pop_off, m + d.m_off, q, tl.y, tl.z, 0);
+        collide_block<2, S, BX, BY, 1, true>(src + d.pop_off, dst + d.pop_off, m + d.m_off, q, tl.y, tl.z, 0);
         __syncthreads();  // the next tile reuses the LDS staging buffers
     }
 }
@@ -249,9 +250,10 @@ struct BDispatchS {
     default: BDispatchS<EVLBM_BF16DEV>::call; break;            \
     }
 
+// One step: the collision sums each tile's halo moments from the pulled
+// populations (the one-pass D2Q9 step), so no moment pass runs.
 void bstep(evlbm_batch *b)
 {
-    if (!b->m_valid) BATCH_DISPATCH(moments(b, b->buf[b->cur]));
     BATCH_DISPATCH(collide(b, b->buf[b->cur], b->buf[1 - b->cur]));
     b->cur = 1 - b->cur;
     b->m_valid = false;

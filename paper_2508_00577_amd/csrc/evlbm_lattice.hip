@@ -69,7 +69,7 @@ struct Ops {
     using R = RealT<S>;
     // tile of the collision kernel
     static constexpr int BX = (D == 2) ? 64 : (S == EVLBM_F64 ? 16 : 32);
-    static constexpr int BY = 4;
+    static constexpr int BY = (D == 2) ? 16 : 4;  // D2Q9: 64 x 16 measured best for the one-pass step
     static constexpr int BZ = (D == 2) ? 1 : 2;
 
     static void moments(evlbm_lattice *h, const void *pop)
@@ -130,9 +130,15 @@ struct Ops {
         if constexpr (D == 3) {
             collide_zm<false>(h, src, dst);
         } else {
+            // D2Q9: the one-pass step sums the moments of its halo from the
+            // pulled populations in the collision itself (no moment pass)
             dim3 grid((h->nx + BX - 1) / BX, (h->ny + BY - 1) / BY, (h->nz + BZ - 1) / BZ);
-            hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ>), grid, dim3(BX, BY, BZ), 0, h->stream, (const T *)src,
-                               (T *)dst, (const R *)h->m, make_params<R>(h));
+            if (h->push)
+                hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ, true>), grid, dim3(BX, BY, BZ), 0, h->stream,
+                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h));
+            else
+                hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ>), grid, dim3(BX, BY, BZ), 0, h->stream,
+                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h));
         }
     }
     static void init(evlbm_lattice *h, const double *rho, const double *u, const double *T0)
@@ -346,13 +352,15 @@ int scan_nonfinite(evlbm_lattice *h)
 
 // Does the step push the next moments (D3Q27 one-pass step)?
 static bool pushes(const evlbm_lattice *h) { return h->D == 3 && h->push && h->shell != nullptr; }
+// the one-pass D2Q9 step: the collision sums its halo's moments itself
+static bool fused(const evlbm_lattice *h) { return h->D == 2 && h->push; }
 
 // One step: moments of the current buffer, collision into the other.  The
 // one-pass D3Q27 step also leaves the moments of the new state in m_alt,
-// which becomes m.
+// which becomes m; the one-pass D2Q9 step needs no moments.
 void launch_step(evlbm_lattice *h, hipEvent_t between)
 {
-    refresh_moments(h);
+    if (!fused(h)) refresh_moments(h);
     const int nxt = 1 - h->cur;
     if (pushes(h)) {
         dispatch<RunCollidePush>(h, (const void *)h->buf[h->cur], h->buf[nxt], between);
@@ -932,11 +940,12 @@ int evlbm_profile_step(evlbm_t h, int nsteps, double out[2])
     for (auto &x : ev)
         if (e == hipSuccess) e = hipEventCreate(&x);
     if (e == hipSuccess) {
-        // two-pass step: [moments] [collision]; one-pass: [collision] [fix-up]
+        // two-pass step: [moments] [collision]; one-pass D3Q27: [collision]
+        // [fix-up]; one-pass D2Q9: [nothing] [collision]
         const bool push = pushes(h);
         for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
             e = hipEventRecord(ev[3 * k], h->stream);
-            if (!push) {
+            if (!push && !fused(h)) {
                 h->m_valid = false;
                 refresh_moments(h);
             }

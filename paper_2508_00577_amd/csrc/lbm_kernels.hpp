@@ -69,11 +69,13 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, c
 
 // ------------------------------------------------------------ k_moments
 
-// m[0] = rho, m[1..D] = j, m[D+1] = e of the pulled populations
-// fh_i(x) = f_i(x - c_i).  Grid (ceil(nx/bx), ny, nz), block (bx).
-template <int D, int S>
-__device__ inline void moments_at(const StoreT<S> *__restrict__ pop, RealT<S> *__restrict__ m,
-                                  const StepParams<RealT<S>> &p, int x, int y, int z)
+// Raw moments of the pulled populations fh_i(x) = f_i(x - c_i), gh_i
+// likewise, of cell (x, y, z) (the density and the sums of eq. u_shift and
+// eq. T_shift before their force terms): out = {rho, jx, jy, jz, e}, each
+// summed in direction order.  With RHO_ONLY only rho (from f alone).
+template <int D, int S, bool RHO_ONLY = false>
+__device__ inline void pulled_moments(const StoreT<S> *__restrict__ pop, const StepParams<RealT<S>> &p, int x, int y,
+                                      int z, RealT<S> out[5])
 {
     using R = RealT<S>;
     constexpr int Q = Lat<D>::Q;
@@ -83,22 +85,40 @@ __device__ inline void moments_at(const StoreT<S> *__restrict__ pop, RealT<S> *_
     for (int i = 0; i < Q; ++i) {
         const unsigned s = o.ox[cx_of(i) + 1] + o.oy[cy_of(i) + 1] + o.oz[cz_d<D>(i) + 1];
         const R f = Codec<S>::dec(ld_at(pop + (long)i * p.ds, s), ref_at_b<D, S>(p, i, s));
-        const R g = Codec<S>::dec(ld_at(pop + (long)(Q + i) * p.ds, s), ref_at_b<D, S>(p, Q + i, s));
         rho += f;
-        e += g;
-        if (cx_of(i) == 1) jx += f;
-        if (cx_of(i) == -1) jx -= f;
-        if (cy_of(i) == 1) jy += f;
-        if (cy_of(i) == -1) jy -= f;
-        if (cz_d<D>(i) == 1) jz += f;
-        if (cz_d<D>(i) == -1) jz -= f;
+        if constexpr (!RHO_ONLY) {
+            const R g = Codec<S>::dec(ld_at(pop + (long)(Q + i) * p.ds, s), ref_at_b<D, S>(p, Q + i, s));
+            e += g;
+            if (cx_of(i) == 1) jx += f;
+            if (cx_of(i) == -1) jx -= f;
+            if (cy_of(i) == 1) jy += f;
+            if (cy_of(i) == -1) jy -= f;
+            if (cz_d<D>(i) == 1) jz += f;
+            if (cz_d<D>(i) == -1) jz -= f;
+        }
     }
+    out[0] = rho;
+    out[1] = jx;
+    out[2] = jy;
+    out[3] = jz;
+    out[4] = e;
+}
+
+// m[0] = rho, m[1..D] = j, m[D+1] = e of the pulled populations
+// fh_i(x) = f_i(x - c_i).  Grid (ceil(nx/bx), ny, nz), block (bx).
+template <int D, int S>
+__device__ inline void moments_at(const StoreT<S> *__restrict__ pop, RealT<S> *__restrict__ m,
+                                  const StepParams<RealT<S>> &p, int x, int y, int z)
+{
+    using R = RealT<S>;
+    R mo[5];
+    pulled_moments<D, S>(pop, p, x, y, z, mo);
     const unsigned c = ((unsigned)x + (unsigned)p.nx * ((unsigned)y + (unsigned)p.ny * (unsigned)z)) * (unsigned)sizeof(R);
-    st_at(m, c, rho);
-    st_at(m + p.N, c, jx);
-    st_at(m + 2 * p.N, c, jy);
-    if (D == 3) st_at(m + 3 * p.N, c, jz);
-    st_at(m + (D + 1) * p.N, c, e);
+    st_at(m, c, mo[0]);
+    st_at(m + p.N, c, mo[1]);
+    st_at(m + 2 * p.N, c, mo[2]);
+    if (D == 3) st_at(m + 3 * p.N, c, mo[3]);
+    st_at(m + (D + 1) * p.N, c, mo[4]);
 }
 
 template <int D, int S>
@@ -319,8 +339,11 @@ struct TileShape {
 };
 
 // One BX x BY x BZ tile of cells with origin (x0, y0, z0); the block's
-// threads are (threadIdx.x, threadIdx.y, threadIdx.z).
-template <int D, int S, int BX, int BY, int BZ>
+// threads are (threadIdx.x, threadIdx.y, threadIdx.z).  With FUSED (the
+// one-pass D2Q9 step) rho on tile + 3 and j, e on tile + 1 are summed here
+// from the pulled populations, in the order of the moment kernel, instead of
+// read from m (not used), so the step needs no moment pass.
+template <int D, int S, int BX, int BY, int BZ, bool FUSED = false>
 __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
                                      const RealT<S> *__restrict__ m, const StepParams<RealT<S>> &p, int x0, int y0,
                                      int z0)
@@ -342,7 +365,13 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
         const int lx = t % TS::R3X, ly = (t / TS::R3X) % TS::R3Y, lz = t / (TS::R3X * TS::R3Y);
         const int gx = wrapi(x0 + lx - 3, p.nx), gy = wrapi(y0 + ly - 3, p.ny);
         const int gz = HZ ? wrapi(z0 + lz - 3, p.nz) : 0;
-        s_rho[t] = m[(long)gx + (long)p.nx * ((long)gy + (long)p.ny * gz)];
+        if constexpr (FUSED) {
+            R mo[5];
+            pulled_moments<D, S, true>(src, p, gx, gy, gz, mo);
+            s_rho[t] = mo[0];
+        } else {
+            s_rho[t] = m[(long)gx + (long)p.nx * ((long)gy + (long)p.ny * gz)];
+        }
     }
     __syncthreads();
 
@@ -371,15 +400,25 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
                         : R(0);
         const int gx = wrapi(x0 + lx - 1, p.nx), gy = wrapi(y0 + ly - 1, p.ny);
         const int gz = HZ ? wrapi(z0 + lz - 1, p.nz) : 0;
-        const long cell = (long)gx + (long)p.nx * ((long)gy + (long)p.ny * gz);
+        R mj[3], me;
+        if constexpr (FUSED) {
+            R mo[5];
+            pulled_moments<D, S>(src, p, gx, gy, gz, mo);
+            for (int a = 0; a < D; ++a) mj[a] = mo[1 + a];
+            me = mo[4];
+        } else {
+            const long cell = (long)gx + (long)p.nx * ((long)gy + (long)p.ny * gz);
+            for (int a = 0; a < D; ++a) mj[a] = m[(a + 1) * N + cell];
+            me = m[(D + 1) * N + cell];
+        }
         const R ir = rcp(rho);
         R u[3], uF = R(0), u2 = R(0);
         for (int a = 0; a < D; ++a) {
-            u[a] = (m[(a + 1) * N + cell] + R(0.5) * F[a]) * ir;
+            u[a] = (mj[a] + R(0.5) * F[a]) * ir;
             uF += u[a] * F[a];
             u2 += u[a] * u[a];
         }
-        const R rhoE = m[(D + 1) * N + cell] + R(0.5) * uF;
+        const R rhoE = me + R(0.5) * uF;
         // K = (3/2) RT is kept as such: the energy equilibria need (3/2) RT and
         // a round trip through a rounded 2/3 would bias the energy every step.
         const R K = rhoE * ir - R(0.5) * u2;
@@ -432,12 +471,12 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
     collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, inv_omb, theta, u, F, Phi, qp);
 }
 
-template <int D, int S, int BX, int BY, int BZ>
+template <int D, int S, int BX, int BY, int BZ, bool FUSED = false>
 __global__ void __launch_bounds__(BX *BY *BZ)
     k_collide(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
               StepParams<RealT<S>> p)
 {
-    collide_block<D, S, BX, BY, BZ>(src, dst, m, p, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * BZ);
+    collide_block<D, S, BX, BY, BZ, FUSED>(src, dst, m, p, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * BZ);
 }
 
 // ------------------------------------------------------- k_collide_zm (3D)
