@@ -222,7 +222,7 @@ int evlbm_batch_read(evlbm_batch_t b, int k, double *rho, double *u, double *T);
 /* Decoded populations f[9 N_k], g[9 N_k] of domain k (host FP64); blocks. */
 int evlbm_batch_get_populations(evlbm_batch_t b, int k, double *f, double *g);
 
-/* Tile shape of the persistent kernels: 0 = 64x4, 1 = 32x8, 2 = 128x2, 3 = 64x8. */
+/* Tile shape of the persistent kernels: 0 = 64x4, 1 = 64x16 (a single lattice's D2Q9 tile), 2 = 128x2, 3 = 64x8. */
 int evlbm_batch_set_tile(evlbm_batch_t b, int variant);
 
 /* Time `steps` steps with each tile shape on the current state (restored

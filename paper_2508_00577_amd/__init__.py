@@ -289,7 +289,7 @@ class Lattice:
         _check(lib().evlbm_checkpoint_load(self._h, str(path).encode()))
 
 
-TILE_SHAPES = [(64, 4), (32, 8), (128, 2), (64, 8)]
+TILE_SHAPES = [(64, 4), (64, 16), (128, 2), (64, 8)]  # evlbm_batch_set_tile variants
 
 
 class Batch:
