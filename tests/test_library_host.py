@@ -1,0 +1,73 @@
+"""Host-side logic of the C-ABI library that runs without a GPU: argument
+checks that return before any device call, and the host coexistence solver
+(equal pressure and equal chemical potential, Newton) against the oracle's
+independent equal-area construction in the P-v plane."""
+import ctypes
+import os
+
+import pytest
+
+import oracle.thermo as TH
+import synth
+
+OK, EINVAL = 0, -1
+D2Q9, D3Q27 = 2, 3
+F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2508_00577_amd import LIB_PATH, build
+    if not os.path.exists(LIB_PATH):
+        build.build()
+    L = ctypes.CDLL(LIB_PATH)
+    L.evlbm_last_error.restype = ctypes.c_char_p
+    L.evlbm_create.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    L.evlbm_eos_coexistence.argtypes = [ctypes.c_double] * 4 + [ctypes.POINTER(ctypes.c_double)]
+    return L
+
+
+@pytest.mark.parametrize("lattice,nx,ny,nz,storage,why", [
+    (4, 16, 16, 1, F32, "unknown lattice"),
+    (D2Q9, 16, 16, 1, 7, "unknown storage"),
+    (D2Q9, 0, 16, 1, F32, "zero size"),
+    (D3Q27, 16, -3, 16, F32, "negative size"),
+    (D2Q9, 16, 16, 2, F32, "D2Q9 with nz != 1"),
+    (D3Q27, 1024, 1024, 1024, F32, "a direction array of 4 GiB"),
+    (D3Q27, 1024, 1024, 512, F64, "a direction array of 4 GiB in FP64"),
+])
+def test_create_rejects_bad_arguments_before_any_device_call(lib, lattice, nx, ny, nz, storage, why):
+    h = ctypes.c_void_p(1)
+    rc = lib.evlbm_create(lattice, nx, ny, nz, storage, None, ctypes.byref(h))
+    assert rc == EINVAL, why
+    assert h.value is None, "the handle must be cleared on failure"
+    assert lib.evlbm_last_error(), "a message for the caller"
+
+
+def test_create_rejects_a_null_handle_pointer(lib):
+    assert lib.evlbm_create(D2Q9, 16, 16, 1, F32, None, None) == EINVAL
+
+
+@pytest.mark.parametrize("Tr", [0.55, 0.65, 0.75, 0.85, 0.95, 0.99])
+def test_host_coexistence_matches_oracle_equal_area(lib, Tr):
+    T = Tr * synth.T_CRIT
+    out = (ctypes.c_double * 3)()
+    assert lib.evlbm_eos_coexistence(synth.R_GAS, synth.A_ATTR, synth.B_EXCL, T, out) == OK
+    rl, rv, P = TH.coexistence(T, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
+    print(f"T/Tc {Tr}: library {out[0]:.15g} {out[1]:.15g} {out[2]:.15g}, oracle {rl:.15g} {rv:.15g} {P:.15g}")
+    assert abs(out[0] - rl) <= 1e-9 * rl
+    assert abs(out[1] - rv) <= 1e-9 * rv
+    assert abs(out[2] - P) <= 1e-9 * abs(P)
+
+
+@pytest.mark.parametrize("R,a,b,T", [
+    (1.0, synth.A_ATTR, synth.B_EXCL, synth.T_CRIT),        # at T_c: no two phases
+    (1.0, synth.A_ATTR, synth.B_EXCL, 1.2 * synth.T_CRIT),  # above T_c
+    (1.0, synth.A_ATTR, synth.B_EXCL, 0.0),
+    (1.0, synth.A_ATTR, 0.0, 0.5 * synth.T_CRIT),           # no excluded volume
+    (1.0, 0.0, synth.B_EXCL, 0.5 * synth.T_CRIT),           # no attraction
+    (0.0, synth.A_ATTR, synth.B_EXCL, 0.5 * synth.T_CRIT),
+])
+def test_host_coexistence_rejects_states_without_two_phases(lib, R, a, b, T):
+    out = (ctypes.c_double * 3)()
+    assert lib.evlbm_eos_coexistence(R, a, b, T, out) == EINVAL
