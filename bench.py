@@ -112,6 +112,50 @@ def cpu_baseline(target_seconds=12.0):
                       f"threads, then 2 steps ({dt1:.1f} s) on one"}
 
 
+def run_2d(ev, synth, extras, laplace=True):
+    """The D2Q9 workloads, results into `extras`: the 512^2 FP32 droplet (with
+    `laplace`, continued to 2e4 steps for the spurious currents and the
+    Laplace pressure jump) and the 64-domain batched sweep."""
+    import torch  # noqa: F401  (device memory and streams)
+    # 2D droplet workload (512^2, FP32, R = 40, T/Tc = 0.8)
+    L2 = make_droplet(ev, synth, (1, 512, 512), 40.0, 0.8, "f32")
+    L2.step(64)
+    t = timed_steps(L2, 2048, sums_every=1024)
+    extras["d2q9_512sq_f32_MLUPS"] = round(512 * 512 * 2048 / t / 1e6, 1)
+    if laplace:
+        L2.step(20000 - 64 - 2048)
+        s2 = L2.global_sums()
+        md = L2.measure_droplet((255.5, 255.5), 20.0, 60.0)
+        extras["d2q9_512sq_R40_Tr08_at_2e4_steps"] = {
+            "max_u": s2[6], "dp": md[4] - md[5], "R_e": md[6], "dp_times_R_e": (md[4] - md[5]) * md[6],
+            "T_liquid_over_Tc": md[2] / synth.T_CRIT, "T_vapour_over_Tc": md[3] / synth.T_CRIT}
+    del L2
+    # batched sweep: 64 uneven D2Q9 domains (64^2 .. 512^2), T/Tc in [0.65, 0.97], FP32
+    table = synth.batch_table()
+    B = ev.Batch([(d["nx"], d["ny"]) for d in table], storage="f32")
+    B.set_params(**synth.params())
+    for k, d in enumerate(table):
+        T0 = d["Tr"] * synth.T_CRIT
+        rl, rv, _ = ev.eos_coexistence(T0, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
+        shp = (1, d["ny"], d["nx"])
+        rho = (synth.slab(shp, rl, rv, noise=1e-3, seed=d["seed"]) if d["kind"] == "slab" else
+               synth.droplet(shp, d["R"], rl, rv, noise=1e-4, seed=d["seed"]))
+        B.init_domain(k, rho, np.full(shp, T0))
+    tune = B.autotune(steps=10)
+    B.step(64)
+    B.synchronize()
+    t0 = time.perf_counter()
+    B.step(512)
+    B.synchronize()
+    tb = time.perf_counter() - t0
+    info = B.info()
+    extras["batch64_MLUPS"] = round(info["cells"] * 512 / tb / 1e6, 1)
+    extras["batch64_cells"] = info["cells"]
+    extras["batch64_tile"] = list(info["tile"])
+    extras["batch64_autotune_ms_per_step"] = [round(x, 4) for x in tune["ms_per_step"]]
+    del B
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +164,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--only-2d", action="store_true",
+                    help="time only the D2Q9 workloads (512^2 droplet, 64-domain batch), e.g. under a profiler")
     ap.add_argument("--long-precision", action="store_true",
                     help="compare the 16-bit storages with FP32 after 1e4 steps instead of 1e3")
     args = ap.parse_args()
@@ -133,6 +179,12 @@ def main():
     import synth
 
     torch.cuda.init()
+    if args.only_2d:
+        extras = {}
+        run_2d(ev, synth, extras, laplace=False)
+        print(json.dumps({"metric": "MLUPS (D2Q9 FP32: 512^2 droplet, 64-domain batched sweep)", "unit": "MLUPS",
+                          "n_gpus": 1, "data": "synthetic", "extras": extras}), flush=True)
+        return
     n = args.n
     shape = (n, n, n)
     cells = n ** 3
@@ -188,43 +240,7 @@ def main():
 
     if not args.no_extras:
         extras = {}
-        # 2D droplet workload (512^2, FP32, R = 40, T/Tc = 0.8), then on to
-        # 2e4 steps: spurious currents (max |u|) and the Laplace pressure jump
-        L2 = make_droplet(ev, synth, (1, 512, 512), 40.0, 0.8, "f32")
-        L2.step(64)
-        t = timed_steps(L2, 2048, sums_every=1024)
-        extras["d2q9_512sq_f32_MLUPS"] = round(512 * 512 * 2048 / t / 1e6, 1)
-        L2.step(20000 - 64 - 2048)
-        s2 = L2.global_sums()
-        md = L2.measure_droplet((255.5, 255.5), 20.0, 60.0)
-        extras["d2q9_512sq_R40_Tr08_at_2e4_steps"] = {
-            "max_u": s2[6], "dp": md[4] - md[5], "R_e": md[6], "dp_times_R_e": (md[4] - md[5]) * md[6],
-            "T_liquid_over_Tc": md[2] / synth.T_CRIT, "T_vapour_over_Tc": md[3] / synth.T_CRIT}
-        del L2
-        # batched sweep: 64 uneven D2Q9 domains (64^2 .. 512^2), T/Tc in [0.65, 0.97], FP32
-        table = synth.batch_table()
-        B = ev.Batch([(d["nx"], d["ny"]) for d in table], storage="f32")
-        B.set_params(**synth.params())
-        for k, d in enumerate(table):
-            T0 = d["Tr"] * synth.T_CRIT
-            rl, rv, _ = ev.eos_coexistence(T0, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
-            shp = (1, d["ny"], d["nx"])
-            rho = (synth.slab(shp, rl, rv, noise=1e-3, seed=d["seed"]) if d["kind"] == "slab" else
-                   synth.droplet(shp, d["R"], rl, rv, noise=1e-4, seed=d["seed"]))
-            B.init_domain(k, rho, np.full(shp, T0))
-        tune = B.autotune(steps=10)
-        B.step(64)
-        B.synchronize()
-        t0 = time.perf_counter()
-        B.step(512)
-        B.synchronize()
-        tb = time.perf_counter() - t0
-        info = B.info()
-        extras["batch64_MLUPS"] = round(info["cells"] * 512 / tb / 1e6, 1)
-        extras["batch64_cells"] = info["cells"]
-        extras["batch64_tile"] = list(info["tile"])
-        extras["batch64_autotune_ms_per_step"] = [round(x, 4) for x in tune["ms_per_step"]]
-        del B
+        run_2d(ev, synth, extras)
         # mixed precision: 16-bit deviation storage against FP32 on the same 3D
         # workload (density error after `cmp` steps; the full 1e4-step horizon
         # with --long-precision)
