@@ -1,15 +1,21 @@
 // HIP kernels of one lattice: initialisation, pulled moments, the fused
 // stencil + collision step, readout, FP64 reductions and region means.
 //
-// One time step (eq. pre_LBM) is two launches:
-//   k_moments  pull f, g (H1) and form rho, j = sum c f, e = sum g (H2) into a
-//              moment field;
+// One time step (eq. pre_LBM), in its two-pass form:
+//   k_moments  pull f, g and form rho, j = sum c f, e = sum g into a moment
+//              field (the sums of eq. u_shift, eq. T_shift);
 //   k_collide  stage rho (tile + 3 halo) in LDS, build lap rho, the force
-//              F = a grad(rho^2) + kappa rho grad(lap rho) (H3), the half-step
-//              fields u, RT, theta = RT/(1 - b rho) (H4) on tile + 1, the
-//              corrections Phi_aa, Phi', q' (H5) and shifted state (H6) on the
-//              tile, then per cell pull f, g again, evaluate the equilibria
-//              (H7), relax (H8) and store (H9).
+//              F = a grad(rho^2) + kappa rho grad(lap rho) (eq. EVforce1 with
+//              eq. P0E), the half-step fields u, RT, theta = RT/(1 - b rho) on
+//              tile + 1, the corrections Phi_aa, Phi', q' (eq. correction_u,
+//              correction_gamma, correction_q) and the shifted state (eq.
+//              def_ustar) on the tile, then per cell pull f, g again, evaluate
+//              the equilibria (eq. feq, f_star, geq, gstar, g_corr), relax and
+//              store.
+// The one-pass steps need no k_moments launch: in D3Q27 the z-marching
+// collision pushes the next step's moments (k_collide_zm<..., PUSH> with
+// k_push_fixup); in D2Q9 the collision sums its halo's moments from the
+// pulled populations (collide_block<..., FUSED>).
 #pragma once
 
 #include <type_traits>
