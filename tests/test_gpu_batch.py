@@ -39,7 +39,7 @@ def _batch(storage, variant=0):
 
 @pytest.mark.parametrize("storage,steps", [("f32", 70), ("f64", 70), ("f16dev", 230)])
 def test_batch_domain_equals_single_lattice_bitwise(storage, steps):
-    """PIN-18: with the same tile shape (64 x 16, a single lattice's D2Q9 tile)
+    """With the same tile shape (64 x 16, a single lattice's D2Q9 tile)
     a batched domain evolves bit for bit as the same domain stepped alone (16-bit storage: across two
     re-references, at steps 100 and 200)."""
     b, fields = _batch(storage, 1)

@@ -37,7 +37,7 @@ def test_forward_matches_oracle(n):
 
 
 def test_gradient_matches_oracle():
-    """PIN-19 (GPU part): per-tensor relative L2 error of the FP32 gradient
+    """Per-tensor relative L2 error of the FP32 gradient
     against the FP64 oracle below 1e-4."""
     p = _params(3)
     X, Y = _batch(777, 4)

@@ -323,7 +323,7 @@ def test_16bit_long_horizon_3d():
 
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
 def test_long_run_mass_is_conserved(storage):
-    """PIN-6 on the GPU over 1e5 steps of a near-steady droplet (96^2): the
+    """On the GPU, over 1e5 steps of a near-steady droplet (96^2): the
     stored populations keep their total mass.  Near a steady state a cell
     rounds the same way every step; closing each cell's balance on the rest
     direction alone let that rounding accumulate (-3.2 of 3882 after 2e5 FP32

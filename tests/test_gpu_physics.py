@@ -1,7 +1,7 @@
 """Physics of the GPU path: the FP64 region measurement against a host
 recomputation from the read-out fields, the flat-interface surface tension
-against the square-gradient first integral (PIN-12) and Laplace's law on
-droplets (PIN-13)."""
+against the square-gradient first integral and Laplace's law on
+droplets."""
 import math
 
 import numpy as np
@@ -70,7 +70,7 @@ def test_measure_droplet_matches_host_recompute(D, shape, R):
 
 @pytest.mark.parametrize("Tr", [0.7, 0.8, 0.9])
 def test_flat_interface_surface_tension(Tr):
-    """PIN-12: sigma = kappa sum_x (d rho/dx)^2 across one interface of a
+    """sigma = kappa sum_x (d rho/dx)^2 across one interface of a
     relaxed flat slab matches sigma = int sqrt(2 kappa dOmega) d rho of the vdW
     free energy at the measured liquid temperature.  Measured ratio after
     6e4 steps: 0.984, 0.974, 0.985 at T/Tc = 0.7, 0.8, 0.9; the bound allows
@@ -96,7 +96,7 @@ def test_flat_interface_surface_tension(Tr):
 
 
 def test_laplace_law_2d():
-    """PIN-13: droplets R = 30, 40, 60 on a 512^2 periodic D2Q9 lattice at
+    """Droplets R = 30, 40, 60 on a 512^2 periodic D2Q9 lattice at
     T/Tc = 0.8 (FP32, 6e4 steps): the pressure jump between the bulk phases
     falls as 1/R_e with slope sigma.  The fitted slope through the origin
     (measured 0.0209) is within 5 % of the flat-interface tension of the

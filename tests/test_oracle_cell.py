@@ -48,7 +48,7 @@ def test_weights_match_golden():
 
 
 def test_psi_moments():
-    """PIN-1: sum_c Psi = 1, sum_c c Psi = xi, sum_c c^2 Psi = zeta (eq. phi)."""
+    """sum_c Psi = 1, sum_c c Psi = xi, sum_c c^2 Psi = zeta (eq. phi)."""
     for _ in range(50):
         xi, zeta = RNG.uniform(-1, 1), RNG.uniform(0, 1)
         ps = {c: O.psi(c, xi, zeta) for c in (-1, 0, 1)}
@@ -59,7 +59,7 @@ def test_psi_moments():
 
 @pytest.mark.parametrize("D", [2, 3])
 def test_feq_and_fstar_moments(D):
-    """PIN-2: rho, rho u and rho u u + P0 I for f^eq (eq. feq); diagonal
+    """rho, rho u and rho u u + P0 I for f^eq (eq. feq); diagonal
     rho zeta* for f* (eq. f_star) with the off-diagonal rho u*_a u*_b."""
     for _ in range(30):
         rho = RNG.uniform(0.05, 2.5)
@@ -89,7 +89,7 @@ def test_feq_and_fstar_moments(D):
 
 @pytest.mark.parametrize("D", [2, 3])
 def test_geq_moments(D):
-    """PIN-2 for eq. geq.  From O_a A = theta dA/du_a + u_a A and
+    """The moments of eq. geq.  From O_a A = theta dA/du_a + u_a A and
     E = (3/2)RT + |u|^2/2, worked by hand:
       sum g = rho E,
       sum c_a g = rho O_a E = u_a (rho E + P0),
@@ -115,7 +115,7 @@ def test_geq_moments(D):
 
 
 def test_d3q27_sums_to_d2q9():
-    """PIN-9 at cell level: summing D3Q27 over c_z with u_z = 0 gives D2Q9."""
+    """At cell level, summing D3Q27 over c_z with u_z = 0 gives D2Q9."""
     c3, _ = O.lattice(3)
     c2, _ = O.lattice(2)
     for _ in range(20):
@@ -144,7 +144,7 @@ def _random_state(D):
 
 
 def test_kop_idempotent_and_orthogonal():
-    """PIN-3: K(K(J)) = K(J) and K(J - K(J)) = 0 (text after eq. def_ustar)."""
+    """K(K(J)) = K(J) and K(J - K(J)) = 0 (text after eq. def_ustar)."""
     worst = 0.0
     for _ in range(300):
         rho, u, RT, J = _random_state(3)
@@ -158,7 +158,7 @@ def test_kop_idempotent_and_orthogonal():
 
 
 def test_kop_local_part_conserves():
-    """PIN-3: J_loc = J - K(J) conserves mass, momentum and kinetic energy."""
+    """J_loc = J - K(J) conserves mass, momentum and kinetic energy."""
     c, _ = O.lattice(3)
     c = c.astype(np.float64)
     for _ in range(200):
@@ -174,7 +174,7 @@ def test_kop_local_part_conserves():
 
 
 def test_kop_linear_limit():
-    """PIN-4: K_lambda -> (1/rho) df^eq/du . F + (2/(3 rho)) df^eq/dRT Qt as
+    """K_lambda -> (1/rho) df^eq/du . F + (2/(3 rho)) df^eq/dRT Qt as
     lambda -> 0 (eq. lim_projection), with an O(lambda) remainder."""
     c, _ = O.lattice(3)
     c = c.astype(np.float64)
@@ -201,7 +201,7 @@ def test_kop_linear_limit():
 
 
 def test_stencils_exact_and_second_order():
-    """PIN-10: the isotropic gradient is exact on quadratics, the Laplacian on
+    """The isotropic gradient is exact on quadratics, the Laplacian on
     cubics (checked away from the periodic seam), and on sin(kx) they give
     sin(k) cos(kx) and 2(cos k - 1) sin(kx) respectively."""
     for D, shape in ((2, (1, 24, 20)), (3, (14, 12, 10))):

@@ -30,7 +30,7 @@ def _lattice(D, shape, **kw):
 
 @pytest.mark.parametrize("D,shape", [(2, (1, 6, 7)), (3, (5, 4, 6))])
 def test_uniform_states_are_fixed_points(D, shape):
-    """PIN-7/8: a uniform state at rest or in uniform motion is unchanged by the
+    """A uniform state at rest or in uniform motion is unchanged by the
     step: streaming a uniform field is the identity, all stencils vanish, so
     F = Phi = q' = 0 and f* = f^eq = fh."""
     L = _lattice(D, shape)
@@ -59,7 +59,7 @@ def _slab_state(D, shape, Tr=0.9, noise=1e-3):
 
 @pytest.mark.parametrize("D,shape", [(2, (1, 12, 40)), (3, (6, 8, 40))])
 def test_collision_conserves_locally(D, shape):
-    """PIN-5: per cell, sum f is unchanged, sum c f gains F dt, sum g gains
+    """Per cell, sum f is unchanged, sum c f gains F dt, sum g gains
     (u.F + Qtilde) dt with Qtilde = 0 (eq. pre_LBM with eq. u_shift, T_shift)."""
     L = _lattice(D, shape)
     rho, T = _slab_state(D, shape)
@@ -83,7 +83,7 @@ def test_collision_conserves_locally(D, shape):
 
 @pytest.mark.parametrize("D,shape,steps", [(2, (1, 16, 48), 300), (3, (8, 8, 24), 40)])
 def test_global_mass_conserved(D, shape, steps):
-    """PIN-6: total mass is invariant on a periodic lattice."""
+    """Total mass is invariant on a periodic lattice."""
     L = _lattice(D, shape)
     rho, T = _slab_state(D, shape)
     L.init(rho, T)
@@ -94,7 +94,7 @@ def test_global_mass_conserved(D, shape, steps):
 
 
 def test_d3q27_with_one_plane_equals_d2q9():
-    """PIN-9: a D3Q27 lattice one cell thick in z reproduces D2Q9 field by field."""
+    """A D3Q27 lattice one cell thick in z reproduces D2Q9 field by field."""
     shape2 = (1, 10, 36)
     rho, T = _slab_state(2, shape2)
     L2 = _lattice(2, shape2)
@@ -152,7 +152,7 @@ def _decay(mode, sphi=-1.0, RT=0.02, lam=1.0, nx=128, steps=3000, A=1e-4, kind="
 
 @pytest.mark.parametrize("RT", [0.05, 0.15])
 def test_ideal_gas_sound_attenuation_decides_phi_sign(RT):
-    """PIN-14a: with a = b = kappa = 0 the model is a compressible Navier-Stokes
+    """With a = b = kappa = 0 the model is a compressible Navier-Stokes
     fluid with nu = tau P0/rho, zero bulk viscosity and Pr = 1, so a standing
     sound wave decays at (k^2/2)[(4/3) nu + (gamma - 1) chi] = nu k^2 and
     oscillates at sqrt(5/3 RT) k.  The lattice third moment c^3 = c misses the
@@ -178,7 +178,7 @@ def test_ideal_gas_sound_attenuation_decides_phi_sign(RT):
 
 @pytest.mark.parametrize("lam", [1.0, 2.0])
 def test_ideal_gas_shear_and_thermal_decay(lam):
-    """PIN-14b,c: shear and isobaric temperature modes decay at nu k^2
+    """Shear and isobaric temperature modes decay at nu k^2
     (Pr = 1: chi = k/(rho c_p) = nu), independently of lambda."""
     k = 2 * np.pi / 128
     RT = 0.05
@@ -190,7 +190,7 @@ def test_ideal_gas_shear_and_thermal_decay(lam):
 
 
 def test_vdw_sound_speed():
-    """PIN-15: in a stable van der Waals state the adiabatic sound speed is
+    """In a stable van der Waals state the adiabatic sound speed is
     c^2 = (5/3) RT/(1 - b rho)^2 - 2 a rho (c_v = 3R/2, P = P_E - a rho^2)."""
     rho0, Tr = 0.6, 1.3
     RT = Tr * synth.T_CRIT
@@ -216,7 +216,7 @@ def test_vdw_sound_speed():
 
 
 def test_flat_interface_coexistence():
-    """PIN-11 (Fig. 1): the flat liquid-vapour interface of the 128 x 32, T/Tc = 0.9,
+    """Fig. 1: the flat liquid-vapour interface of the 128 x 32, T/Tc = 0.9,
     FP64 workload after 2000 steps.  The liquid sits on Maxwell's equal-area
     density at the measured liquid temperature within 1 %.  The vapour, whose
     temperature lags (latent heat; thermal equilibration across the slab takes

@@ -65,7 +65,7 @@ def _batch(n=37, seed=3):
 
 
 def test_mlp_shapes_and_gradient_matches_finite_differences():
-    """PIN-19: backprop against central differences (h = 1e-6)."""
+    """Backprop against central differences (h = 1e-6)."""
     theta = synth.xavier_params()
     assert theta.size == M.NPARAM == 8641
     theta = theta + 0.05 * np.random.default_rng(1).standard_normal(theta.size)  # non-zero biases
