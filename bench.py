@@ -170,8 +170,8 @@ def main():
                     help="compare the 16-bit storages with FP32 after 1e4 steps instead of 1e3")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the lattice is not sharded across GPUs in this build "
-              "(see the multi-GPU design notes); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library does not shard a lattice across GPUs; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
