@@ -95,11 +95,15 @@ struct Codec<EVLBM_F32> {
     static __device__ inline T enc(R v, Ref<R>) { return v; }
 };
 
+// 16-bit decodes are one explicit fused multiply-add: whether the compiler
+// fuses r + s h on its own depends on the surrounding code, and a stored value
+// must decode to the same bits in every kernel that pulls it (the one-pass and
+// two-pass steps agree bit for bit).
 template <>
 struct Codec<EVLBM_F16DEV> {
     using T = uint16_t;
     using R = float;
-    static __device__ inline R dec(T v, Ref<R> q) { return q.r + q.s * f16_to_f32(v); }
+    static __device__ inline R dec(T v, Ref<R> q) { return __builtin_fmaf(q.s, f16_to_f32(v), q.r); }
     static __device__ inline T enc(R v, Ref<R> q) { return f32_to_f16_rne((v - q.r) * q.is); }
 };
 
@@ -107,7 +111,7 @@ template <>
 struct Codec<EVLBM_BF16DEV> {
     using T = uint16_t;
     using R = float;
-    static __device__ inline R dec(T v, Ref<R> q) { return q.r + q.s * bf16_to_f32(v); }
+    static __device__ inline R dec(T v, Ref<R> q) { return __builtin_fmaf(q.s, bf16_to_f32(v), q.r); }
     static __device__ inline T enc(R v, Ref<R> q) { return f32_to_bf16_rne((v - q.r) * q.is); }
 };
 
@@ -282,10 +286,12 @@ __device__ inline Ref<R> ref_value(int pop, float4 rs)
     constexpr int Q = Lat<D>::Q;
     const int i = pop < Q ? pop : pop - Q;
     const int n = cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_d<D>(i) * cz_d<D>(i);
+    static_assert(sizeof(R) == 4, "16-bit storage decodes in FP32");
     R f = (R)rs.x;
     for (int k = 0; k < n; ++k) f *= (R)rs.y;
     if (pop < Q) return Ref<R>{f, f, R(0)};
-    return Ref<R>{f * ((R)rs.z + R(n) * (R)rs.w), f * (R)rs.w, R(0)};
+    // A + n B as one explicit fused multiply-add (see the 16-bit codecs)
+    return Ref<R>{f * __builtin_fmaf(R(n), (R)rs.w, (R)rs.z), f * (R)rs.w, R(0)};
 }
 
 // The reciprocals an encoding cell needs, computed once per cell.

@@ -78,8 +78,8 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, c
 // Raw moments of the pulled populations fh_i(x) = f_i(x - c_i), gh_i
 // likewise, of cell (x, y, z) (the density and the sums of eq. u_shift and
 // eq. T_shift before their force terms): out = {rho, jx, jy, jz, e}, each
-// summed in direction order.  With RHO_ONLY only rho (from f alone).
-template <int D, int S, bool RHO_ONLY = false>
+// summed in direction order.  WITH_F: rho and j (from f); WITH_G: e (from g).
+template <int D, int S, bool WITH_F = true, bool WITH_G = true>
 __device__ inline void pulled_moments(const StoreT<S> *__restrict__ pop, const StepParams<RealT<S>> &p, int x, int y,
                                       int z, RealT<S> out[5])
 {
@@ -90,17 +90,19 @@ __device__ inline void pulled_moments(const StoreT<S> *__restrict__ pop, const S
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const unsigned s = o.ox[cx_of(i) + 1] + o.oy[cy_of(i) + 1] + o.oz[cz_d<D>(i) + 1];
-        const R f = Codec<S>::dec(ld_at(pop + (long)i * p.ds, s), ref_at_b<D, S>(p, i, s));
-        rho += f;
-        if constexpr (!RHO_ONLY) {
-            const R g = Codec<S>::dec(ld_at(pop + (long)(Q + i) * p.ds, s), ref_at_b<D, S>(p, Q + i, s));
-            e += g;
+        if constexpr (WITH_F) {
+            const R f = Codec<S>::dec(ld_at(pop + (long)i * p.ds, s), ref_at_b<D, S>(p, i, s));
+            rho += f;
             if (cx_of(i) == 1) jx += f;
             if (cx_of(i) == -1) jx -= f;
             if (cy_of(i) == 1) jy += f;
             if (cy_of(i) == -1) jy -= f;
             if (cz_d<D>(i) == 1) jz += f;
             if (cz_d<D>(i) == -1) jz -= f;
+        }
+        if constexpr (WITH_G) {
+            const R g = Codec<S>::dec(ld_at(pop + (long)(Q + i) * p.ds, s), ref_at_b<D, S>(p, Q + i, s));
+            e += g;
         }
     }
     out[0] = rho;
@@ -348,7 +350,9 @@ struct TileShape {
 // threads are (threadIdx.x, threadIdx.y, threadIdx.z).  With FUSED (the
 // one-pass D2Q9 step) rho on tile + 3 and j, e on tile + 1 are summed here
 // from the pulled populations, in the order of the moment kernel, instead of
-// read from m (not used), so the step needs no moment pass.
+// read from m (not used), so the step needs no moment pass: rho and j from
+// one pull of f in the rho stage (j kept in LDS for tile + 1), e from a pull
+// of g in the field stage.
 template <int D, int S, int BX, int BY, int BZ, bool FUSED = false>
 __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
                                      const RealT<S> *__restrict__ m, const StepParams<RealT<S>> &p, int x0, int y0,
@@ -362,6 +366,7 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
     __shared__ R s_rho[TS::N3];
     __shared__ R s_lap[TS::N2];
     __shared__ R s_f1[TS::NF * TS::N1];
+    __shared__ R s_j[FUSED ? D : 1][FUSED ? TS::N1 : 1];  // FUSED: j on tile + 1, from the rho stage's pulls
 
     const int tid = threadIdx.x + BX * (threadIdx.y + BY * threadIdx.z);
     const long N = p.N;
@@ -373,8 +378,11 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
         const int gz = HZ ? wrapi(z0 + lz - 3, p.nz) : 0;
         if constexpr (FUSED) {
             R mo[5];
-            pulled_moments<D, S, true>(src, p, gx, gy, gz, mo);
+            pulled_moments<D, S, true, false>(src, p, gx, gy, gz, mo);
             s_rho[t] = mo[0];
+            const int l1x = lx - 2, l1y = ly - 2, l1z = lz - 2 * HZ;
+            if (l1x >= 0 && l1x < TS::R1X && l1y >= 0 && l1y < TS::R1Y && l1z >= 0 && l1z < TS::R1Z)
+                for (int a = 0; a < D; ++a) s_j[a][l1x + TS::R1X * (l1y + TS::R1Y * l1z)] = mo[1 + a];
         } else {
             s_rho[t] = m[(long)gx + (long)p.nx * ((long)gy + (long)p.ny * gz)];
         }
@@ -409,8 +417,8 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
         R mj[3], me;
         if constexpr (FUSED) {
             R mo[5];
-            pulled_moments<D, S>(src, p, gx, gy, gz, mo);
-            for (int a = 0; a < D; ++a) mj[a] = mo[1 + a];
+            pulled_moments<D, S, false, true>(src, p, gx, gy, gz, mo);
+            for (int a = 0; a < D; ++a) mj[a] = s_j[a][t];
             me = mo[4];
         } else {
             const long cell = (long)gx + (long)p.nx * ((long)gy + (long)p.ny * gz);
