@@ -68,7 +68,12 @@ __global__ void __launch_bounds__(BX *BY)
                     const DomainRec *__restrict__ dom, const int4 *__restrict__ tiles, int ntiles,
                     StepParams<RealT<S>> p)
 {
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // rounds of gridDim.x consecutive tiles; within a full round each XCD
+    // takes a contiguous run of the list (xcd_tile), neighbouring tiles of
+    // one domain, so their shared halo lines meet in one L2
+    for (int r = 0; r < ntiles; r += gridDim.x) {
+        const int t = r + (ntiles - r >= (int)gridDim.x ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x);
+        if (t >= ntiles) break;
         const int4 tl = tiles[t];
         const DomainRec d = dom[tl.x];
         const StepParams<RealT<S>> q = domain_params(p, d);

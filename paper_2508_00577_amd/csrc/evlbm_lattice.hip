@@ -132,13 +132,14 @@ struct Ops {
         } else {
             // D2Q9: the one-pass step sums the moments of its halo from the
             // pulled populations in the collision itself (no moment pass)
-            dim3 grid((h->nx + BX - 1) / BX, (h->ny + BY - 1) / BY, (h->nz + BZ - 1) / BZ);
+            const int nbx = (h->nx + BX - 1) / BX, nby = (h->ny + BY - 1) / BY, nbz = (h->nz + BZ - 1) / BZ;
+            const int nt = nbx * nby * nbz;
             if (h->push)
-                hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ, true>), grid, dim3(BX, BY, BZ), 0, h->stream,
-                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h));
+                hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ, true>), dim3(nt), dim3(BX, BY, BZ), 0, h->stream,
+                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, nt);
             else
-                hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ>), grid, dim3(BX, BY, BZ), 0, h->stream,
-                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h));
+                hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ>), dim3(nt), dim3(BX, BY, BZ), 0, h->stream,
+                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, nt);
         }
     }
     static void init(evlbm_lattice *h, const double *rho, const double *u, const double *T0)

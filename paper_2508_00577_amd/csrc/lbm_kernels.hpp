@@ -333,6 +333,19 @@ __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S>
 
 // ------------------------------------------------------------ k_collide
 
+// Tile of block b (tiles x fastest, then y, then the z chunk; T tiles per
+// chunk).  Workgroups are dealt round-robin to the 8 XCDs, each with its own
+// L2: XCD j gets the j-th eighth of every chunk, whole rows of tiles, so
+// tiles that share halo lines are resident on the same L2 while all XCDs
+// stream the same chunk (HBM page locality).  Identity when 8 does not
+// divide T; a bijection either way.
+__device__ inline int xcd_tile(int b, int T)
+{
+    if (T & 7) return b;
+    const int per = T >> 3, j = b & 7, k = b >> 3;
+    return (k / per) * T + j * per + k % per;
+}
+
 template <int D, int BX, int BY, int BZ>
 struct TileShape {
     static constexpr int HZ = Lat<D>::HZ;
@@ -485,12 +498,14 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
     collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, inv_omb, theta, u, F, Phi, qp);
 }
 
+// One tile per workgroup, nbx x nby x nbz tiles in XCD order (xcd_tile).
 template <int D, int S, int BX, int BY, int BZ, bool FUSED = false>
 __global__ void __launch_bounds__(BX *BY *BZ)
     k_collide(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
-              StepParams<RealT<S>> p)
+              StepParams<RealT<S>> p, int nbx, int nby, int ntiles)
 {
-    collide_block<D, S, BX, BY, BZ, FUSED>(src, dst, m, p, blockIdx.x * BX, blockIdx.y * BY, blockIdx.z * BZ);
+    const int t = xcd_tile(blockIdx.x, ntiles), bxy = t % (nbx * nby);
+    collide_block<D, S, BX, BY, BZ, FUSED>(src, dst, m, p, (bxy % nbx) * BX, (bxy / nbx) * BY, (t / (nbx * nby)) * BZ);
 }
 
 // ------------------------------------------------------- k_collide_zm (3D)
@@ -575,19 +590,6 @@ __device__ inline R ring_lap(const R *pm, const R *p0, const R *pp, int c, int s
 }
 
 __device__ inline int ring_slot(int k, int n) { return (k + 8 * n) % n; }
-
-// Tile of block b (tiles x fastest, then y, then the z chunk; T tiles per
-// chunk).  Workgroups are dealt round-robin to the 8 XCDs, each with its own
-// L2: XCD j gets the j-th eighth of every chunk, whole rows of tiles, so
-// tiles that share halo lines are resident on the same L2 while all XCDs
-// stream the same chunk (HBM page locality).  Identity when 8 does not
-// divide T; a bijection either way.
-__device__ inline int xcd_tile(int b, int T)
-{
-    if (T & 7) return b;
-    const int per = T >> 3, j = b & 7, k = b >> 3;
-    return (k / per) * T + j * per + k % per;
-}
 
 // Moments of the next step pushed by the collision (one-pass step).  The
 // next step's rho, j and e of a cell are sums over the values stored at its
