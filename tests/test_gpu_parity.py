@@ -86,6 +86,25 @@ def test_one_step_populations_f64(D, shape):
     assert ef < 1e-13 and eg < 1e-13
 
 
+def test_2d_tiles_in_xcd_order_f64():
+    """A 250 x 120 lattice has 4 x 8 = 32 tiles of 64 x 16, ragged in x and
+    y, which its launch deals to the 8 XCDs in bands (a non-trivial order:
+    32 is a multiple of 8 above 8).  Populations and moments after 20 steps
+    against the oracle."""
+    shape = (1, 120, 250)
+    rho, T = _state("droplet", shape, 0.8, 1e-3)
+    g, o = _pair(2, shape, "f64", rho, T)
+    g.step(20)
+    o.step(20)
+    fg, gg = g.get_populations()
+    fo, go = o.get_pops()
+    ef = np.abs(fg - fo).max() / np.abs(fo).max()
+    eg = np.abs(gg - go).max() / np.abs(go).max()
+    print(f"250 x 120, 20 steps: e_f={ef:.2e} e_g={eg:.2e}", flush=True)
+    assert ef < 1e-12 and eg < 1e-12
+    _compare(g, o, 1e-10, "250 x 120 f64, 20 steps")
+
+
 def test_c1_flat_interface_f64_1000_steps():
     """128 x 32 flat interface, T/Tc = 0.9, FP64: moments after 1, 100 and 1000 steps."""
     shape = (1, 32, 128)
