@@ -112,6 +112,33 @@ def cpu_baseline(target_seconds=12.0):
                       f"threads, then 2 steps ({dt1:.1f} s) on one"}
 
 
+def run_laplace_grid(ev, synth, steps=20000, n=512):
+    """The 512^2 static-droplet grid, R in {20, 30, 40, 60} x T/Tc in {0.7,
+    0.8, 0.9, 0.95}, FP32, seeded +-1e-4 noise: per case after `steps` steps
+    the bulk pressure jump dp and equimolar radius R_e (Laplace: dp R_e ->
+    sigma), the bulk temperatures and the largest speed (the spurious
+    currents), all from the library's FP64 measurement on the GPU."""
+    p = synth.params()
+    rows = []
+    for Tr in (0.7, 0.8, 0.9, 0.95):
+        T0 = Tr * synth.T_CRIT
+        rl, rv, _ = ev.eos_coexistence(T0, p["R"], p["a"], p["b"])
+        for R in (20.0, 30.0, 40.0, 60.0):
+            L = ev.Lattice(2, n, n, 1, storage="f32")
+            L.set_params(**p)
+            L.init_fields(synth.droplet((1, n, n), R, rl, rv, noise=1e-4, seed=synth.SEED + int(100 * Tr) + int(R)),
+                          np.full((1, n, n), T0))
+            L.step(steps)
+            s = L.global_sums()
+            md = L.measure_droplet(((n - 1) / 2, (n - 1) / 2), R / 2, R + 20)
+            rows.append({"Tr": Tr, "R": R, "dp": md[4] - md[5], "R_e": md[6], "dp_times_R_e": (md[4] - md[5]) * md[6],
+                         "T_liquid_over_Tc": md[2] / synth.T_CRIT, "T_vapour_over_Tc": md[3] / synth.T_CRIT,
+                         "max_u": s[6]})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del L
+    return rows
+
+
 def run_2d(ev, synth, extras, laplace=True):
     """The D2Q9 workloads, results into `extras`: the 512^2 FP32 droplet (with
     `laplace`, continued to 2e4 steps for the spurious currents and the
@@ -166,6 +193,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only-2d", action="store_true",
                     help="time only the D2Q9 workloads (512^2 droplet, 64-domain batch), e.g. under a profiler")
+    ap.add_argument("--laplace-grid", action="store_true",
+                    help="run the 512^2 static-droplet grid (R x T/Tc, 2e4 steps) and print its Laplace and "
+                         "spurious-current figures")
     ap.add_argument("--long-precision", action="store_true",
                     help="compare the 16-bit storages with FP32 after 1e4 steps instead of 1e3")
     args = ap.parse_args()
@@ -179,6 +209,10 @@ def main():
     import synth
 
     torch.cuda.init()
+    if args.laplace_grid:
+        print(json.dumps({"workload": "2D static droplets, D2Q9 512^2 periodic, FP32, 2e4 steps",
+                          "cases": run_laplace_grid(ev, synth)}), flush=True)
+        return
     if args.only_2d:
         extras = {}
         run_2d(ev, synth, extras, laplace=False)
