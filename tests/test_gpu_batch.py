@@ -98,6 +98,46 @@ def test_batch_with_more_tiles_than_the_grid(storage):
         assert ef < 1e-12 and eg < 1e-12
 
 
+# domains smaller than the radius-3 stencil halo, one row or column of tiles
+# thick, next to an ordinary one
+TINY = [("droplet", 1, 1, 0.8), ("slab", 2, 3, 0.85), ("slab", 5, 70, 0.7), ("droplet", 70, 5, 0.9),
+        ("droplet", 40, 33, 0.8)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_batch_tiny_domains(storage):
+    """Each tiny domain evolves bit for bit as the same domain stepped alone
+    (same 64 x 16 tile), its periodic images wrapping inside the tile; in
+    FP64 every domain also matches the oracle."""
+    b = ev.Batch([(nx, ny) for _, nx, ny, _ in TINY], storage=storage)
+    b.set_params(**P)
+    b.set_tile(1)
+    fields = []
+    for k, (kind, nx, ny, Tr) in enumerate(TINY):
+        fields.append(_fields(kind, nx, ny, Tr, synth.SEED * 1000 + 80 + k))
+        b.init_domain(k, *fields[k])
+    print(f"tiny domains {[(nx, ny) for _, nx, ny, _ in TINY]}, {storage}", flush=True)
+    b.step(40)
+    for k, (kind, nx, ny, Tr) in enumerate(TINY):
+        L = ev.Lattice(2, nx, ny, 1, storage=storage)
+        L.set_params(**P)
+        L.init_fields(*fields[k])
+        L.step(40)
+        fa, ga = b.get_populations(k)
+        fb, gb = L.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), f"domain {k} ({nx} x {ny})"
+        if storage == "f64":
+            o = oracle.Lattice(2, nx, ny, 1)
+            o.set_params(**P)
+            o.init(*fields[k])
+            o.step(40)
+            fo, go = o.get_pops()
+            ef = np.abs(fa - fo).max() / np.abs(fo).max()
+            eg = np.abs(ga - go).max() / np.abs(go).max()
+            print(f"  {nx} x {ny} against the oracle: e_f={ef:.2e} e_g={eg:.2e}", flush=True)
+            assert ef < 1e-12 and eg < 1e-12, f"domain {k} ({nx} x {ny})"
+
+
 def test_batch_graph_replays_match_eager_steps():
     """Steps replayed from the captured 32-step graph (a call of 64 steps: two
     replays) give the same bits as the same steps launched eagerly (calls of
