@@ -193,6 +193,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--only-2d", action="store_true",
                     help="time only the D2Q9 workloads (512^2 droplet, 64-domain batch), e.g. under a profiler")
+    ap.add_argument("--only-mlp", action="store_true",
+                    help="time only the warm-start network's training (1152 seeded samples, 300 Adam iterations), "
+                         "e.g. under a profiler")
     ap.add_argument("--laplace-grid", action="store_true",
                     help="run the 512^2 static-droplet grid (R x T/Tc, 2e4 steps) and print its Laplace and "
                          "spurious-current figures")
@@ -209,6 +212,19 @@ def main():
     import synth
 
     torch.cuda.init()
+    if args.only_mlp:
+        rng = np.random.default_rng(synth.SEED + 7)
+        n = 1152  # 72 waves of 16 samples; the shape of the droplet-profile training sets
+        X = np.stack([rng.uniform(0.72, 0.88, n), rng.uniform(10.0, 22.0, n), rng.uniform(0.0, 3.0, n)], 1)
+        Y = 1.0 + 0.8 * np.tanh(4.0 * (1.0 - X[:, 2]))
+        net = ev.MLP(synth.xavier_params())
+        net.train(X, Y, 20, 1e-3)
+        t0 = time.perf_counter()
+        net.train(X, Y, 300, 1e-3)
+        dt = time.perf_counter() - t0
+        print(json.dumps({"workload": "warm-start network training, 1152 samples, 300 Adam iterations",
+                          "us_per_iteration": round(dt / 300 * 1e6, 1)}), flush=True)
+        return
     if args.laplace_grid:
         print(json.dumps({"workload": "2D static droplets, D2Q9 512^2 periodic, FP32, 2e4 steps",
                           "cases": run_laplace_grid(ev, synth)}), flush=True)
