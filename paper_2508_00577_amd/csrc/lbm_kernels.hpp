@@ -339,7 +339,7 @@ __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S>
 // tiles that share halo lines are resident on the same L2 while all XCDs
 // stream the same chunk (HBM page locality).  Identity when 8 does not
 // divide T; a bijection either way.
-__device__ inline int xcd_tile(int b, int T)
+__host__ __device__ inline int xcd_tile(int b, int T)
 {
     if (T & 7) return b;
     const int per = T >> 3, j = b & 7, k = b >> 3;

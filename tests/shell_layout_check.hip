@@ -2,8 +2,8 @@
 // own Shell<TX, TY, ZC>): for every tile chunk extent W <= TX, H <= TY,
 // Zc <= ZC, the targets a chunk writes to its shell (the tile + 1 ring of each
 // of its planes, the whole tile + 1 face below and above) get distinct slots
-// inside [0, SIZE).  Built and run by test_shell_layout.py; exit status 0 on
-// success.
+// inside [0, SIZE); and the XCD order of the tile launches (check_xcd).
+// Built and run by test_shell_layout.py; exit status 0 on success.
 #include <cstdio>
 #include <vector>
 
@@ -48,7 +48,47 @@ static int check()
     return 0;
 }
 
+// The XCD order of the tile launches (xcd_tile): for T tiles per chunk and
+// nchunk chunks, the map of block indices onto tiles is a bijection of
+// [0, T nchunk) (no tile skipped or run twice), and when 8 divides T the
+// blocks of one XCD (equal b mod 8) take one contiguous run of every chunk.
+static int check_xcd()
+{
+    for (int T = 1; T <= 1100; ++T)
+        for (int nchunk : {1, 3, 7}) {
+            const int n = T * nchunk;
+            std::vector<int> seen(n, 0);
+            for (int b = 0; b < n; ++b) {
+                const int t = evlbm::xcd_tile(b, T);
+                if (t < 0 || t >= n || seen[t]++) {
+                    std::printf("xcd_tile: T %d, %d chunks: block %d -> tile %d out of range or repeated\n", T,
+                                nchunk, b, t);
+                    return 1;
+                }
+            }
+            if (T % 8) continue;
+            for (int c = 0; c < nchunk; ++c)
+                for (int j = 0; j < 8; ++j) {
+                    int lo = n, hi = -1, count = 0;
+                    for (int b = 0; b < n; ++b) {
+                        const int t = evlbm::xcd_tile(b, T);
+                        if ((b & 7) == j && t / T == c) {
+                            lo = t < lo ? t : lo;
+                            hi = t > hi ? t : hi;
+                            ++count;
+                        }
+                    }
+                    if (count != T / 8 || hi - lo + 1 != count) {
+                        std::printf("xcd_tile: T %d, chunk %d, XCD %d: tiles not one contiguous run of %d\n", T, c,
+                                    j, T / 8);
+                        return 1;
+                    }
+                }
+        }
+    return 0;
+}
+
 int main()
 {
-    return check<64, 4, 40>() | check<16, 8, 64>() | check<16, 8, 40>() | check<64, 4, 32>();
+    return check<64, 4, 40>() | check<16, 8, 64>() | check<16, 8, 40>() | check<64, 4, 32>() | check_xcd();
 }

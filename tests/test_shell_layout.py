@@ -1,7 +1,9 @@
 """The shell of partial moment sums a tile chunk leaves for its neighbours
 (the one-pass step) gives every target cell around the chunk its own slot:
 the library's slot functions, compiled for the host and checked over every
-chunk extent (no GPU needed)."""
+chunk extent (no GPU needed).  The same program checks that the XCD order of
+the tile launches is a bijection onto the tiles with one contiguous run of
+each chunk per XCD."""
 import os
 import shutil
 import subprocess
