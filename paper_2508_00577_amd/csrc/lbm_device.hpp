@@ -269,13 +269,13 @@ __device__ inline PullOffsets pull_offsets(int nx, int ny, int nz, int x, int y,
 // chi(0) = -theta^2 and chi(+-1) = theta^2/2 divided by psi).  A cell stores
 // the state as {a0, q, A, B}; scales are f^eq for f and B f^eq for g (both
 // positive).
-template <int D>
-__host__ __device__ inline float4 ref_state_of(double rho, double theta, double K)
+template <int D, typename V = double>
+__host__ __device__ inline float4 ref_state_of(V rho, V theta, V K)
 {
-    const double w0 = 1.0 - theta, w1 = 0.5 * theta;
-    double a0 = rho;
+    const V w0 = V(1) - theta, w1 = V(0.5) * theta;
+    V a0 = rho;
     for (int k = 0; k < D; ++k) a0 *= w0;
-    return make_float4((float)a0, (float)(w1 / w0), (float)(K - D * theta * theta / w0), (float)(theta / w0));
+    return make_float4((float)a0, (float)(w1 / w0), (float)(K - V(D) * theta * theta / w0), (float)(theta / w0));
 }
 
 // Reference value and scale of population pop (f 0..Q-1, then g) for a cell

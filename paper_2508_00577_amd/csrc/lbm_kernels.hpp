@@ -154,24 +154,72 @@ __device__ inline void pull_pops(const A &pops, const PullOffsets &o, StoreT<S> 
     }
 }
 
+// Error-free sums for the conservation closure, in the arithmetic type.
+// Knuth's TwoSum (TAOCP vol. 2, 4.2.2): s = fl(a + b) and e with s + e = a + b
+// exactly, for any a, b (6 operations).
+template <typename R>
+__device__ inline void two_sum(R a, R b, R &s, R &e)
+{
+    s = a + b;
+    const R bv = s - a;
+    e = (a - (s - bv)) + (b - bv);
+}
+
+// A sum carried as hi + lo.  add() is Dekker's Fast2Sum (1971): for
+// |hi| >= |x|, s = fl(hi + x) and x - (s - hi) is the exact rounding error of
+// s, which lo collects (3 operations and one add).  The collision starts hi
+// at the cell's rest population, the largest population whenever
+// theta + u_a^2 + |u_a| < 2 (1 - theta - u_a^2) on every axis (all the states
+// of these workloads), and adds and subtracts single populations, so the
+// error terms are exact; lo rounds only sums of errors that are each below
+// half an ulp of hi, i.e. the pair carries ~2^-48 of the cell's mass.
+template <typename R>
+struct Compensated {
+    R hi, lo;
+    __device__ inline void add(R x)
+    {
+        const R s = hi + x;
+        lo += x - (s - hi);
+        hi = s;
+    }
+    // exact product a b = p + e (e from a fused multiply-add) added in
+    __device__ inline void add_product(R a, R b)
+    {
+        const R pr = a * b;
+        R e;
+        if constexpr (sizeof(R) == 4)
+            e = __builtin_fmaf(a, b, -pr);
+        else
+            e = __builtin_fma(a, b, -pr);
+        add(pr);
+        lo += e;
+    }
+};
+
 // Store the rest direction r and the opposite pair a, b of a cell so that
-// their three stored values sum to `total` (exact FP64) up to the pair's own
-// rounding: r gets total - na - nb, the pair its updates na, nb plus half of
-// the rest's rounding residual each (b also absorbs a's rounding).  The
-// values the three stored words decode to are returned in out (r, a, b).
+// their three stored values sum to the compensated total t up to the pair's
+// own rounding: r gets t - na - nb, the pair its updates na, nb plus half of
+// the rest's rounding residual each (b also absorbs a's rounding).  The two
+// differences of nearby values that carry the balance (t - r, pair - a) are
+// formed exactly with TwoSum.  The values the three stored words decode to
+// are returned in out (r, a, b).
 template <int S, class A>
-__device__ inline void close_three(const A &pops, unsigned cell, int r, int a, int b, double total, RealT<S> na,
-                                   RealT<S> nb, Ref<RealT<S>> qr, Ref<RealT<S>> qa, Ref<RealT<S>> qb,
+__device__ inline void close_three(const A &pops, unsigned cell, int r, int a, int b, Compensated<RealT<S>> t,
+                                   RealT<S> na, RealT<S> nb, Ref<RealT<S>> qr, Ref<RealT<S>> qa, Ref<RealT<S>> qb,
                                    RealT<S> out[3])
 {
     using R = RealT<S>;
-    const StoreT<S> vr = Codec<S>::enc((R)(total - (double)na - (double)nb), qr);
+    const StoreT<S> vr = Codec<S>::enc(((t.hi - na) - nb) + t.lo, qr);
     out[0] = Codec<S>::dec(vr, qr);
-    const double pair = total - (double)out[0];                      // what a + b must carry
-    const double half = 0.5 * (pair - (double)na - (double)nb);      // half the rest's residual
-    const StoreT<S> va = Codec<S>::enc((R)((double)na + half), qa);
+    R ph, pl;  // what a + b must carry: t - out[0] = ph + pl
+    two_sum(t.hi, -out[0], ph, pl);
+    pl += t.lo;
+    const R half = R(0.5) * (((ph - na) - nb) + pl);  // half the rest's residual
+    const StoreT<S> va = Codec<S>::enc(na + half, qa);
     out[1] = Codec<S>::dec(va, qa);
-    const StoreT<S> vb = Codec<S>::enc((R)(pair - (double)out[1]), qb);
+    R bh, bl;  // what b must carry: ph + pl - out[1]
+    two_sum(ph, -out[1], bh, bl);
+    const StoreT<S> vb = Codec<S>::enc(bh + (bl + pl), qb);
     out[2] = Codec<S>::dec(vb, qb);
     pops.st(r, cell, vr);
     pops.st(a, cell, va);
@@ -236,9 +284,10 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
 
     // The collision conserves mass and energy exactly: sum f_new = sum fh and
     // sum g_new = sum gh + u.F (eq. pre_LBM with eq. u_shift, T_shift and
-    // Qtilde = 0).  Three directions are stored last, after the exact (FP64)
-    // sums of the incoming values and of the values actually stored in the
-    // others: the rest direction takes the remainder less the updates of the
+    // Qtilde = 0).  Three directions are stored last, after the compensated
+    // sums (Compensated: error-free in the arithmetic type) of the incoming
+    // values less the values actually stored in the others, with u.F added as
+    // exact products: the rest direction takes the remainder less the updates of the
     // two all-diagonal directions c = +-(1, 1[, 1]), and that pair (the
     // smallest populations, ~ (theta/2)^D rho) shares what the rounded rest
     // value leaves, half each, the second member taking the first's rounding
@@ -253,7 +302,7 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
     const RefInv<R> invc = ref_inv_of<S, R>(rsc);
     const R fh_rest = Codec<S>::dec(fr[REST], ref_enc<D, S>(REST, rsc, invc));
     const R gh_rest = Codec<S>::dec(gr[REST], ref_enc<D, S>(Q + REST, rsc, invc));
-    double mass = (double)fh_rest, energy = (double)gh_rest, sf = 0.0, sg = 0.0;
+    Compensated<R> mass{fh_rest, R(0)}, energy{gh_rest, R(0)};
     R fn_a = R(0), gn_a = R(0), fn_b = R(0), gn_b = R(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -274,8 +323,8 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
         // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq)
         const R fn = omb * fh + c_eq * feq + p.wstar * fst;
         const R gn = omb * gh + c_eq * geq + p.wstar * gst;
-        mass += (double)fh;
-        energy += (double)gh;
+        mass.add(fh);
+        energy.add(gh);
         if (i == SA) {
             fn_a = fn;
             gn_a = gn;
@@ -298,15 +347,16 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
         // measured slower.)
         if constexpr (sizeof(StoreT<S>) >= 4) __builtin_amdgcn_sched_barrier(0);
         const R fd = Codec<S>::dec(fq, rf), gd = Codec<S>::dec(gq, rg);
-        sf += (double)fd;
-        sg += (double)gd;
+        mass.add(-fd);
+        energy.add(-gd);
         sink(i, fd, gd);
     }
-    const double uF = (double)u[0] * F[0] + (double)u[1] * F[1] + (double)u[2] * F[2];
+#pragma unroll
+    for (int a = 0; a < D; ++a) energy.add_product(u[a], F[a]);
     R cf[3], cg[3];
-    close_three<S>(pops, cell, REST, SA, SB, mass - sf, fn_a, fn_b, ref_enc<D, S>(REST, rsc, invc),
+    close_three<S>(pops, cell, REST, SA, SB, mass, fn_a, fn_b, ref_enc<D, S>(REST, rsc, invc),
                    ref_enc<D, S>(SA, rsc, invc), ref_enc<D, S>(SB, rsc, invc), cf);
-    close_three<S>(pops, cell, Q + REST, Q + SA, Q + SB, energy + uF - sg, gn_a, gn_b,
+    close_three<S>(pops, cell, Q + REST, Q + SA, Q + SB, energy, gn_a, gn_b,
                    ref_enc<D, S>(Q + REST, rsc, invc), ref_enc<D, S>(Q + SA, rsc, invc),
                    ref_enc<D, S>(Q + SB, rsc, invc), cg);
     sink(REST, cf[0], cg[0]);
@@ -1518,21 +1568,22 @@ __global__ void __launch_bounds__(256) k_ref_from_fields(const double *__restric
 }
 
 // The same from populations f, g at rest in the cell's own frame: rho = sum f,
-// j = sum c f, K = sum g/rho - |j|^2/(2 rho^2) = (3/2) RT.
-template <int D>
-__device__ inline float4 ref_state(const double *f, const double *g, double b)
+// j = sum c f, K = sum g/rho - |j|^2/(2 rho^2) = (3/2) RT, in the arithmetic
+// type V (the reference only sets the scale of the stored deviations).
+template <int D, typename V>
+__device__ inline float4 ref_state(const V *f, const V *g, V b)
 {
     constexpr int Q = Lat<D>::Q;
-    double rho = 0.0, e = 0.0, j[3] = {0.0, 0.0, 0.0};
+    V rho = V(0), e = V(0), j[3] = {V(0), V(0), V(0)};
     for (int i = 0; i < Q; ++i) {
         rho += f[i];
         e += g[i];
-        j[0] += cx_of(i) * f[i];
-        j[1] += cy_of(i) * f[i];
-        j[2] += cz_d<D>(i) * f[i];
+        j[0] += V(cx_of(i)) * f[i];
+        j[1] += V(cy_of(i)) * f[i];
+        j[2] += V(cz_d<D>(i)) * f[i];
     }
-    const double K = e / rho - 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / (rho * rho);
-    return ref_state_of<D>(rho, (2.0 / 3.0) * K / (1.0 - b * rho), K);
+    const V K = e / rho - V(0.5) * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / (rho * rho);
+    return ref_state_of<D, V>(rho, (V(2) / V(3)) * K / (V(1) - b * rho), K);
 }
 
 // From decoded populations in the dense host layout ([Q][N] f, then g).
@@ -1563,36 +1614,37 @@ __global__ void __launch_bounds__(256) k_rereference(StoreT<S> *__restrict__ pop
     constexpr int Q = Lat<D>::Q;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= p.N) return;
-    double f[Q], g[Q];
+    using R = RealT<S>;
+    R f[Q], g[Q];
     for (int i = 0; i < Q; ++i) {
-        f[i] = (double)Codec<S>::dec(pop[(long)i * p.ds + t], ref_at<D, S>(p, i, t));
-        g[i] = (double)Codec<S>::dec(pop[(long)(Q + i) * p.ds + t], ref_at<D, S>(p, Q + i, t));
+        f[i] = Codec<S>::dec(pop[(long)i * p.ds + t], ref_at<D, S>(p, i, t));
+        g[i] = Codec<S>::dec(pop[(long)(Q + i) * p.ds + t], ref_at<D, S>(p, Q + i, t));
     }
-    const float4 rs = ref_state<D>(f, g, (double)p.b);
+    const float4 rs = ref_state<D, R>(f, g, p.b);
     refst[t] = rs;
     const RefInv<RealT<S>> inv = ref_inv_of<S, RealT<S>>(rs);
     // re-encode keeping the cell's mass and energy: rest + opposite pair close
     // the balances as in the collision
     constexpr int REST = (Q - 1) / 2, SA = Q - 1, SB = 0;
-    using R = RealT<S>;
     const PtrPops<StoreT<S>> pops{pop, pop, p.ds};
     const unsigned cb = (unsigned)t * (unsigned)sizeof(StoreT<S>);
-    double mf = 0.0, mg = 0.0, sf = 0.0, sg = 0.0;
+    Compensated<R> mf{f[REST], R(0)}, mg{g[REST], R(0)};  // Fast2Sum from the largest population
     for (int i = 0; i < Q; ++i) {
-        mf += f[i];
-        mg += g[i];
-        if (i == REST || i == SA || i == SB) continue;
+        if (i == REST) continue;
+        mf.add(f[i]);
+        mg.add(g[i]);
+        if (i == SA || i == SB) continue;
         const Ref<R> rf = ref_enc<D, S>(i, rs, inv), rg = ref_enc<D, S>(Q + i, rs, inv);
-        const StoreT<S> fq = Codec<S>::enc((R)f[i], rf), gq = Codec<S>::enc((R)g[i], rg);
+        const StoreT<S> fq = Codec<S>::enc(f[i], rf), gq = Codec<S>::enc(g[i], rg);
         pops.st(i, cb, fq);
         pops.st(Q + i, cb, gq);
-        sf += (double)Codec<S>::dec(fq, rf);
-        sg += (double)Codec<S>::dec(gq, rg);
+        mf.add(-Codec<S>::dec(fq, rf));
+        mg.add(-Codec<S>::dec(gq, rg));
     }
     R cd[3];
-    close_three<S>(pops, cb, REST, SA, SB, mf - sf, (R)f[SA], (R)f[SB], ref_enc<D, S>(REST, rs, inv),
+    close_three<S>(pops, cb, REST, SA, SB, mf, f[SA], f[SB], ref_enc<D, S>(REST, rs, inv),
                    ref_enc<D, S>(SA, rs, inv), ref_enc<D, S>(SB, rs, inv), cd);
-    close_three<S>(pops, cb, Q + REST, Q + SA, Q + SB, mg - sg, (R)g[SA], (R)g[SB], ref_enc<D, S>(Q + REST, rs, inv),
+    close_three<S>(pops, cb, Q + REST, Q + SA, Q + SB, mg, g[SA], g[SB], ref_enc<D, S>(Q + REST, rs, inv),
                    ref_enc<D, S>(Q + SA, rs, inv), ref_enc<D, S>(Q + SB, rs, inv), cd);
 }
 
