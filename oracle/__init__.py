@@ -26,6 +26,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "evo.c")
 _LIB = os.path.join(_HERE, "libevo.so")
 
+EOS_KINDS = {"vdw": 0, "cs": 1}
+
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
 
@@ -59,6 +61,8 @@ def lib():
         L.evo_set_threads.argtypes = [ctypes.c_int]
         L.evo_get_threads.restype = ctypes.c_int
         L.evo_set_params.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 7
+        L.evo_set_eos.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.evo_set_walls.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double]
         L.evo_init.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
         L.evo_get_pops.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.evo_set_pops.argtypes = [ctypes.c_void_p, _dp, _dp]
@@ -175,10 +179,21 @@ class Lattice:
             lib().evo_destroy(h)
             self._h = None
 
-    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0):
+    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0, eos="vdw"):
+        """Model parameters; eos selects the contact factor of Enskog's
+        pressure: "vdw" (the paper's van der Waals form) or "cs"
+        (Carnahan-Starling)."""
         rc = lib().evo_set_params(self._h, R, a, b, kappa, tau, lam, sphi)
         if rc != 0:
             raise ValueError("invalid parameters")
+        if lib().evo_set_eos(self._h, EOS_KINDS[eos]) != 0:
+            raise ValueError("unknown eos")
+
+    def set_walls(self, Tw, Uw, enable=True):
+        """Diffuse walls normal to x at x = -1/2 (at rest) and x = nx - 1/2
+        (moving with Uw along y), both at temperature Tw."""
+        if lib().evo_set_walls(self._h, 1 if enable else 0, float(Tw), float(Uw)) != 0:
+            raise ValueError("walls need nx >= 2 and Tw > 0")
 
     def init(self, rho, T, u=None):
         rho = _f64(rho).reshape(-1)

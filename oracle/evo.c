@@ -29,6 +29,20 @@
  *     g^eq(u*, RT*) with P0/rho evaluated at RT* (eq. gstar).
  *   - The energy half-step uses the total energy of g:
  *     rho E = sum g + (dt/2)(u.F + Qtilde), which equals eq. T_shift.
+ *   - Enskog's pressure P_E = rho R T (1 + b rho chi) with the contact value
+ *     chi of the pair distribution: the van der Waals form the paper uses,
+ *     chi = 1/(1 - b rho), or Carnahan-Starling's hard-sphere value
+ *     chi = (1 - eta/2)/(1 - eta)^3 with eta = b rho/4 (Carnahan & Starling,
+ *     J. Chem. Phys. 51, 635 (1969)).  Either way P_E = rho R T Z(rho) and
+ *     gamma_0 of eq. gamma follows from Z.
+ *   - Walls (the thermal Couette flow after eq. P0E, Fig. 2; optional, normal
+ *     to x at x = -1/2 and x = nx - 1/2, the second moving with U_w along y,
+ *     both at T_w): diffuse reflection.  A population entering the fluid from
+ *     a wall is the wall's equilibrium f^eq(u_w, P0/rho at T_w), g^eq alike,
+ *     times the density that makes the mass entering the cell equal the mass
+ *     its populations send into the wall in the same step.  Stencils read a
+ *     field beyond a wall from its linear extrapolation through the two
+ *     nearest cells.
  *
  * Lattice units: dt = dx = 1, particle mass m = 1 so rho = n.
  */
@@ -48,6 +62,9 @@ typedef struct {
     double w[QMAX];
     /* model parameters */
     double R, a, b, kappa, tau, lambda, sphi;
+    int eos; /* 0: van der Waals contact factor, 1: Carnahan-Starling */
+    int walls;       /* 1: diffuse walls normal to x (see the header) */
+    double Tw, Uw;   /* wall temperature, speed of the wall at x = nx - 1/2 (along y) */
     /* state S_n: post-collision, pre-stream populations, layout [i][cell] */
     double *f, *g;
     /* work fields, one value (or D values, layout [alpha][cell]) per cell */
@@ -100,15 +117,60 @@ static long neighbour(const evo_t *h, long cell, int dx, int dy, int dz)
     return cell_index(h, x, y, z);
 }
 
+/* ----------------------------------------------------- Enskog pressure */
+
+/* Compressibility factor Z = P_E/(rho R T) of Enskog's pressure
+ * P_E = rho R T (1 + b rho chi), and its logarithmic density derivative
+ * d ln Z/d ln rho (both independent of T).
+ *   van der Waals: chi = 1/(1 - b rho), so Z = 1/(1 - b rho) and
+ *     d ln Z/d ln rho = b rho/(1 - b rho);
+ *   Carnahan-Starling: chi = (1 - eta/2)/(1 - eta)^3, eta = b rho/4, so
+ *     Z = 1 + 4 eta chi = (1 + eta + eta^2 - eta^3)/(1 - eta)^3 and
+ *     d ln Z/d ln rho = eta (1 + 2 eta - 3 eta^2)/(1 + eta + eta^2 - eta^3)
+ *                       + 3 eta/(1 - eta).
+ * Returns 0 outside the physical range (b rho >= 1, resp. eta >= 1). */
+static int enskog_factor(const evo_t *h, double rho, double *Z, double *dlnZ)
+{
+    double b = h->b;
+    if (h->eos == 1) {
+        double eta = 0.25 * b * rho;
+        if (!(eta < 1.0)) return 0;
+        double num = 1.0 + eta + eta * eta - eta * eta * eta;
+        double den = (1.0 - eta) * (1.0 - eta) * (1.0 - eta);
+        *Z = num / den;
+        if (dlnZ) *dlnZ = eta * (1.0 + 2.0 * eta - 3.0 * eta * eta) / num + 3.0 * eta / (1.0 - eta);
+        return 1;
+    }
+    if (!(1.0 - b * rho > 0.0)) return 0;
+    *Z = 1.0 / (1.0 - b * rho);
+    if (dlnZ) *dlnZ = b * rho / (1.0 - b * rho);
+    return 1;
+}
+
 /* ------------------------------------------------------------- stencils */
+
+/* Value of field phi at the cell displaced by (dx, dy, dz): periodic, or with
+ * walls, beyond them in x the linear extrapolation through the two cells
+ * next to the wall, phi(e) + k (phi(e) - phi(e -+ 1)) at distance k. */
+static double field_at(const evo_t *h, const double *phi, long cell, int dx, int dy, int dz)
+{
+    int x = (int)(cell % h->nx);
+    if (h->walls && (x + dx < 0 || x + dx >= h->nx)) {
+        int e = (x + dx < 0) ? 0 : h->nx - 1;        /* the cell next to the wall */
+        int in = (x + dx < 0) ? 1 : h->nx - 2;       /* its inner neighbour */
+        int k = (x + dx < 0) ? -(x + dx) : x + dx - (h->nx - 1);
+        long ce = neighbour(h, cell, e - x, dy, dz), ci = neighbour(h, cell, in - x, dy, dz);
+        return phi[ce] + (double)k * (phi[ce] - phi[ci]);
+    }
+    return phi[neighbour(h, cell, dx, dy, dz)];
+}
 
 static double grad_at(const evo_t *h, const double *phi, int a, long cell)
 {
     double s = 0.0;
     for (int i = 0; i < h->Q; i++) {
         if (h->c[i][a] == 0) continue;
-        long nb = neighbour(h, cell, h->c[i][0], h->c[i][1], h->c[i][2]);
-        s += h->w[i] * (double)h->c[i][a] * phi[nb];
+        s += h->w[i] * (double)h->c[i][a] * field_at(h, phi, cell, h->c[i][0], h->c[i][1], h->c[i][2]);
     }
     return 3.0 * s;
 }
@@ -116,10 +178,8 @@ static double grad_at(const evo_t *h, const double *phi, int a, long cell)
 static double lap_at(const evo_t *h, const double *phi, long cell)
 {
     double s = 0.0;
-    for (int i = 0; i < h->Q; i++) {
-        long nb = neighbour(h, cell, h->c[i][0], h->c[i][1], h->c[i][2]);
-        s += h->w[i] * (phi[nb] - phi[cell]);
-    }
+    for (int i = 0; i < h->Q; i++)
+        s += h->w[i] * (field_at(h, phi, cell, h->c[i][0], h->c[i][1], h->c[i][2]) - phi[cell]);
     return 6.0 * s;
 }
 
@@ -309,21 +369,41 @@ int evo_set_params(evo_t *h, double R, double a, double b, double kappa,
     return 0;
 }
 
+/* Contact factor of Enskog's pressure: 0 van der Waals, 1 Carnahan-Starling. */
+int evo_set_eos(evo_t *h, int kind)
+{
+    if (kind != 0 && kind != 1) return -1;
+    h->eos = kind;
+    return 0;
+}
+
+/* Diffuse walls normal to x (see the header): enable, wall temperature T_w,
+ * speed U_w of the wall at x = nx - 1/2 along y (the other is at rest). */
+int evo_set_walls(evo_t *h, int enable, double Tw, double Uw)
+{
+    if (enable && (h->nx < 2 || !(Tw > 0))) return -1;
+    h->walls = enable ? 1 : 0;
+    h->Tw = Tw;
+    h->Uw = Uw;
+    return 0;
+}
+
 /* Initial state: f = f^eq(rho0, u0, P0/rho), g = g^eq(rho0, u0, RT0), stored
  * as the post-collision state S_0. */
 int evo_init(evo_t *h, const double *rho0, const double *u0, const double *T0)
 {
     for (long x = 0; x < h->N; x++) {
-        double r = rho0[x], RT = h->R * T0[x];
-        if (!(r > 0) || !(RT > 0) || !(1.0 - h->b * r > 0)) return -1;
+        double r = rho0[x], RT = h->R * T0[x], Z;
+        if (!(r > 0) || !(RT > 0) || !enskog_factor(h, r, &Z, NULL)) return -1;
     }
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < h->N; x++) {
-        double r = rho0[x], RT = h->R * T0[x];
+        double r = rho0[x], RT = h->R * T0[x], Z;
         double uu[3] = {0, 0, 0};
         if (u0)
             for (int a = 0; a < h->D; a++) uu[a] = u0[a * h->N + x];
-        double theta = RT / (1.0 - h->b * r);
+        enskog_factor(h, r, &Z, NULL);
+        double theta = RT * Z;
         double zeta[3];
         for (int a = 0; a < h->D; a++) zeta[a] = theta + uu[a] * uu[a];
         for (int i = 0; i < h->Q; i++) {
@@ -349,17 +429,51 @@ void evo_set_pops(evo_t *h, const double *f, const double *g)
 
 /* ---------------------------------------------------------- the step */
 
-/* Exact on-lattice propagation (pull form): fh_i(x) = f_i(x - c_i). */
+/* Diffuse re-emission at a wall for cell x next to it: side = -1 (wall at
+ * x = -1/2, at rest) or +1 (wall at x = nx - 1/2, moving with U_w along y).
+ * The populations entering the cell from the wall (c_x = -side) become
+ * rho_w f^eq_i(1, u_w, theta_w) and rho_w g^eq_i(1, u_w, R T_w, theta_w), with
+ * theta_w = R T_w Z(rho) at the cell's stored density and rho_w such that they
+ * carry the mass of the cell's populations heading into the wall (c_x = side). */
+static void wall_emission(evo_t *h, long x, int side)
+{
+    long N = h->N;
+    double rho = 0.0, out = 0.0, in = 0.0, Z = 1.0;
+    for (int i = 0; i < h->Q; i++) {
+        rho += h->f[i * N + x];
+        if (h->c[i][0] == side) out += h->f[i * N + x];
+    }
+    enskog_factor(h, rho, &Z, NULL);
+    double RTw = h->R * h->Tw, theta = RTw * Z;
+    double uw[3] = {0.0, side > 0 ? h->Uw : 0.0, 0.0}, zeta[3];
+    for (int a = 0; a < h->D; a++) zeta[a] = theta + uw[a] * uw[a];
+    for (int i = 0; i < h->Q; i++)
+        if (h->c[i][0] == -side) in += product_population(h, i, 1.0, uw, zeta);
+    double rho_w = out / in;
+    for (int i = 0; i < h->Q; i++)
+        if (h->c[i][0] == -side) {
+            h->fh[i * N + x] = rho_w * product_population(h, i, 1.0, uw, zeta);
+            h->gh[i * N + x] = rho_w * energy_population(h, i, 1.0, uw, RTw, theta);
+        }
+}
+
+/* Exact on-lattice propagation (pull form): fh_i(x) = f_i(x - c_i); with
+ * walls, the populations whose source lies beyond a wall come from it. */
 static void stage_stream(evo_t *h)
 {
     long N = h->N;
 #pragma omp parallel for schedule(static)
-    for (long x = 0; x < N; x++)
+    for (long x = 0; x < N; x++) {
+        int xc = (int)(x % h->nx);
         for (int i = 0; i < h->Q; i++) {
+            if (h->walls && (xc - h->c[i][0] < 0 || xc - h->c[i][0] >= h->nx)) continue;
             long src = neighbour(h, x, -h->c[i][0], -h->c[i][1], -h->c[i][2]);
             h->fh[i * N + x] = h->f[i * N + src];
             h->gh[i * N + x] = h->g[i * N + src];
         }
+        if (h->walls && xc == 0) wall_emission(h, x, -1);
+        if (h->walls && xc == h->nx - 1) wall_emission(h, x, +1);
+    }
 }
 
 /* Raw moments: rho = sum fh, j = sum c fh, e = sum gh. */
@@ -402,7 +516,7 @@ static void stage_force(evo_t *h)
 
 /* Half-step shifted fields (eq. u_shift, eq. T_shift), Qtilde = 0:
  * rho u = j + F/2, rho E = e + u.F/2, (3/2) rho RT = rho E - rho |u|^2/2,
- * P0 = P_E = rho RT/(1 - b rho). */
+ * P0 = P_E = rho RT Z(rho) (Z = 1/(1 - b rho) for van der Waals). */
 static void stage_fields(evo_t *h)
 {
     long N = h->N;
@@ -421,7 +535,9 @@ static void stage_fields(evo_t *h)
         h->rhoE[x] = rhoE;
         double RT = (2.0 / 3.0) * (rhoE / r - 0.5 * u2);
         h->RT[x] = RT;
-        double PE = r * RT / (1.0 - h->b * r);
+        double Z = NAN;
+        enskog_factor(h, r, &Z, NULL); /* NAN outside the physical range: caught by fields_physical */
+        double PE = r * RT * Z;
         h->P0[x] = PE;
         h->Th[x] = PE / r;
     }
@@ -451,13 +567,14 @@ static void stage_corrections(evo_t *h)
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < N; x++) {
         double r = h->rho[x];
-        double one_m_br = 1.0 - h->b * r;
-        /* P0 = P_E = rho R T/(1 - b rho):
-         * (d ln P0/d ln rho)_T = 1/(1 - b rho), (d ln P0/d ln T)_rho = 1,
-         * P_E/(rho R T) = 1/(1 - b rho). */
-        double dlnP_dlnrho = 1.0 / one_m_br;
+        double Z, dlnZ;
+        enskog_factor(h, r, &Z, &dlnZ);
+        /* P0 = P_E = rho R T Z(rho):
+         * (d ln P0/d ln rho)_T = 1 + d ln Z/d ln rho, (d ln P0/d ln T)_rho = 1,
+         * P_E/(rho R T) = Z (van der Waals: 1/(1 - b rho), 1, 1/(1 - b rho)). */
+        double dlnP_dlnrho = 1.0 + dlnZ;
         double dlnP_dlnT = 1.0;
-        double PE_over_rhoRT = 1.0 / one_m_br;
+        double PE_over_rhoRT = Z;
         double gamma0 = dlnP_dlnrho + (2.0 / 3.0) * PE_over_rhoRT * dlnP_dlnT;
         double Phip = h->P0[x] * (5.0 / 3.0 - gamma0) * h->divu[x];
         h->Phip[x] = Phip;
@@ -487,8 +604,10 @@ static void stage_shift(evo_t *h)
             F2 += h->F[a * N + x] * h->F[a * N + x];
         }
         double RTs = h->RT[x] + 2.0 * lam * Qtilde / (3.0 * r) - lam * lam * F2 / (3.0 * r * r);
+        double Z;
+        enskog_factor(h, r, &Z, NULL);
         h->RTs[x] = RTs;
-        h->Ths[x] = RTs / (1.0 - h->b * r);
+        h->Ths[x] = RTs * Z;
     }
 }
 
@@ -557,7 +676,8 @@ static void stage_collide(evo_t *h, double *diag)
 static int fields_physical(const evo_t *h)
 {
     for (long x = 0; x < h->N; x++) {
-        if (!(h->rho[x] > 0) || !(1.0 - h->b * h->rho[x] > 0) || !(h->RT[x] > 0)) return 0;
+        double Z;
+        if (!(h->rho[x] > 0) || !enskog_factor(h, h->rho[x], &Z, NULL) || !(h->RT[x] > 0)) return 0;
     }
     return 1;
 }

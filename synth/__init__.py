@@ -29,9 +29,20 @@ TAU = 1.0
 LAMBDA = 1.0
 RHO_CRIT = 1.0 / (3.0 * B_EXCL)
 
+# The same fluid with Carnahan-Starling's hard-sphere contact factor in
+# Enskog's pressure: round values near the van der Waals critical point above
+# (rho_c ~ 1.003, RT_c ~ 0.01995 with eta_c = b rho_c/4 = 0.1304).
+B_CS = 0.52
+A_CS = 0.0275
+
 
 def params(kappa: float = KAPPA) -> dict:
     return dict(R=R_GAS, a=A_ATTR, b=B_EXCL, kappa=kappa, tau=TAU, lam=LAMBDA)
+
+
+def params_cs(kappa: float = KAPPA) -> dict:
+    """Parameters of the Carnahan-Starling workloads (eos = "cs")."""
+    return dict(R=R_GAS, a=A_CS, b=B_CS, kappa=kappa, tau=TAU, lam=LAMBDA, eos="cs")
 
 
 def uniform_noise(shape, amplitude, seed):
@@ -40,27 +51,55 @@ def uniform_noise(shape, amplitude, seed):
     return amplitude * rng.uniform(-1.0, 1.0, size=shape)
 
 
-def slab(shape, rho_l, rho_v, width=2.0, noise=1e-3, seed=SEED + 1):
-    """Flat liquid slab along x between x = nx/4 and 3nx/4 (two interfaces).
+def splitmix_uniform(n, seed):
+    """The counter-based generator the library's initialisers draw from:
+    splitmix64 (Steele, Lea & Flood, OOPSLA 2014).  Value c (c = 0 .. n-1) is
+    output c + 1 of the stream `seed`: the state seed + (c + 1) gamma,
+    gamma = 0x9E3779B97F4A7C15, mixed by z ^= z >> 30, z *= 0xBF58476D1CE4E5B9,
+    z ^= z >> 27, z *= 0x94D049BB133111EB, z ^= z >> 31 (all modulo 2^64), and
+    taken as a double in [0, 1) from its top 53 bits."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.arange(n, dtype=np.uint64) + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
 
-    rho = rho_v + (rho_l - rho_v)/2 [tanh((x - nx/4)/W) - tanh((x - 3nx/4)/W)],
-    times (1 + noise * U[-1, 1)).
+
+def splitmix_noise(shape, amplitude, seed):
+    """U[-amplitude, amplitude) from splitmix_uniform over the cells in
+    linear order (x fastest)."""
+    n = int(np.prod(shape))
+    return (amplitude * (2.0 * splitmix_uniform(n, seed) - 1.0)).reshape(shape)
+
+
+def _noise(shape, amplitude, seed, rng):
+    return (splitmix_noise if rng == "splitmix" else uniform_noise)(shape, amplitude, seed)
+
+
+def slab(shape, rho_l, rho_v, width=2.0, noise=1e-3, seed=SEED + 1, rng="pcg64", x0=None, x1=None):
+    """Flat liquid slab along x between x0 = nx/4 and x1 = 3nx/4 (two interfaces).
+
+    rho = rho_v + (rho_l - rho_v)/2 [tanh((x - x0)/W) - tanh((x - x1)/W)],
+    times (1 + noise * U[-1, 1)) with U from numpy's PCG64 (rng = "pcg64") or
+    from splitmix_uniform (rng = "splitmix", the library initialisers' noise).
     """
     nz, ny, nx = shape
+    x0 = nx / 4.0 if x0 is None else x0
+    x1 = 3.0 * nx / 4.0 if x1 is None else x1
     x = np.arange(nx, dtype=np.float64)
-    prof = rho_v + 0.5 * (rho_l - rho_v) * (np.tanh((x - nx / 4.0) / width)
-                                             - np.tanh((x - 3.0 * nx / 4.0) / width))
+    prof = rho_v + 0.5 * (rho_l - rho_v) * (np.tanh((x - x0) / width) - np.tanh((x - x1) / width))
     rho = np.broadcast_to(prof, shape).copy()
     if noise:
-        rho *= 1.0 + uniform_noise(shape, noise, seed)
+        rho *= 1.0 + _noise(shape, noise, seed, rng)
     return rho
 
 
-def droplet(shape, radius, rho_l, rho_v, width=2.0, noise=1e-4, seed=SEED + 2, centre=None):
+def droplet(shape, radius, rho_l, rho_v, width=2.0, noise=1e-4, seed=SEED + 2, centre=None, rng="pcg64"):
     """Droplet of radius R centred at (n-1)/2 on every axis (2D when nz = 1).
 
     rho = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh((r - R)/W),
-    times (1 + noise * U[-1, 1)).
+    times (1 + noise * U[-1, 1)) (rng as for slab).
     """
     nz, ny, nx = shape
     if centre is None:
@@ -72,7 +111,7 @@ def droplet(shape, radius, rho_l, rho_v, width=2.0, noise=1e-4, seed=SEED + 2, c
     r = np.sqrt(r2)
     rho = 0.5 * (rho_l + rho_v) - 0.5 * (rho_l - rho_v) * np.tanh((r - radius) / width)
     if noise:
-        rho *= 1.0 + uniform_noise(shape, noise, seed)
+        rho *= 1.0 + _noise(shape, noise, seed, rng)
     return rho
 
 

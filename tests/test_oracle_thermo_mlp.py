@@ -57,6 +57,64 @@ def test_surface_tension_scaling():
     assert TH.surface_tension(0.65 * 0.02, 0.1) > TH.surface_tension(0.9 * 0.02, 0.1) > 0
 
 
+def test_cs_critical_point_and_virial_series():
+    """Carnahan-Starling contact factor with mean-field attraction,
+    P = rho RT Z(eta) - a rho^2, eta = b rho/4: the critical point has
+    eta_c = 0.1304 and Z_c = P_c/(rho_c R T_c) = 0.3590 whatever a and b
+    (R T_c = 0.3773 a/b); the hard-sphere factor reproduces the virial series
+    Z = 1 + 4 eta + 10 eta^2 + 18 eta^3 + ... that the Carnahan-Starling form
+    is built on (its coefficients are n^2 + n - 2)."""
+    for a, b in ((synth.A_CS, synth.B_CS), (0.1, 0.25)):
+        rc, Tc, Pc = TH.critical_point(1.0, a, b, "cs")
+        assert b * rc / 4 == pytest.approx(0.1304, abs=1e-4)
+        assert Pc / (rc * Tc) == pytest.approx(0.3590, abs=1e-4)
+        assert Tc * b / a == pytest.approx(0.3773, abs=1e-4)
+        # the critical point is where dP/drho and d2P/drho2 vanish (central differences)
+        h = 1e-4 * rc
+        P = lambda r: TH.pressure(r, Tc, a, b, "cs")
+        assert abs(P(rc + h) - P(rc - h)) / (2 * h) < 1e-6 * Pc / rc
+        assert abs(P(rc + h) - 2 * P(rc) + P(rc - h)) / h ** 2 < 1e-4 * Pc / rc ** 2
+    b = 0.4
+    for eta in (1e-3, 2e-3):
+        Z = TH.compressibility(4 * eta / b, b, "cs")
+        assert (Z - 1 - 4 * eta - 10 * eta ** 2) / eta ** 3 == pytest.approx(18.0 + 28.0 * eta, rel=1e-3)
+
+
+@pytest.mark.parametrize("Tr", [0.6, 0.75, 0.9, 0.97])
+def test_cs_maxwell_equal_pressure_chemical_potential_and_area(Tr):
+    """The equal-area densities of the Carnahan-Starling fluid have equal
+    pressure and equal chemical potential: the chemical potential by the
+    Gibbs-Duhem integral of (1/rho) dP/drho along the isotherm with dP/drho
+    from finite differences (independent of the closed-form mu), and the
+    closed-form mu agrees; the free energy satisfies rho mu - psi = P."""
+    a, b = synth.A_CS, synth.B_CS
+    _, Tc, _ = TH.critical_point(1.0, a, b, "cs")
+    T = Tr * Tc
+    rl, rv, Pc = TH.coexistence(T, 1.0, a, b, "cs")
+    assert rl > 1.0 > rv > 0
+    assert TH.pressure(rl, T, a, b, "cs") == pytest.approx(Pc, rel=1e-9)
+    assert TH.pressure(rv, T, a, b, "cs") == pytest.approx(Pc, rel=1e-9)
+    dPdr = lambda r: (TH.pressure(r * (1 + 1e-7), T, a, b, "cs") - TH.pressure(r * (1 - 1e-7), T, a, b, "cs")) / (2e-7 * r)
+    dmu, _ = quad(lambda r: dPdr(r) / r, rv, rl, limit=200, epsrel=1e-11)
+    assert abs(dmu) < 1e-7 * T
+    assert TH.chemical_potential(rl, T, a, b, "cs") - TH.chemical_potential(rv, T, a, b, "cs") == \
+        pytest.approx(0.0, abs=1e-9 * T)
+    for r in (rv, 0.5 * (rl + rv), rl):
+        mu = TH.chemical_potential(r, T, a, b, "cs")
+        assert r * mu - TH.free_energy_density(r, T, a, b, "cs") == pytest.approx(TH.pressure(r, T, a, b, "cs"),
+                                                                                  rel=1e-10, abs=1e-15)
+
+
+def test_vdw_free_energy_and_quadrature_construction_agree():
+    """The quadrature form of the equal-area rule (used for any closure)
+    reproduces the closed-form van der Waals construction."""
+    for Tr in (0.65, 0.9):
+        T = Tr * synth.T_CRIT
+        ref = TH.coexistence(T)
+        got = TH._coexistence_quadrature(T, 1.0, synth.A_ATTR, synth.B_EXCL, "vdw")
+        np.testing.assert_allclose(got, ref, rtol=1e-10)
+
+
 def _batch(n=37, seed=3):
     rng = np.random.default_rng(seed)
     X = np.stack([rng.uniform(0.65, 0.95, n), rng.uniform(15, 80, n), rng.uniform(0, 3, n)], 1)
