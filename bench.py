@@ -313,7 +313,9 @@ def main():
         r_ref = r_ref.double()
         del ref
         extras[f"f32_rho_rel_err_vs_f64_at_{cmp}_steps"] = float(((r_ref - r64).abs().max() / r64.abs().max()).item())
-        for st in ("f16dev", "bf16dev"):
+        # FP16 deviations: the 16-bit storage that meets the 1e-3 density bar
+        # (BF16 deviations, experimental in the library, miss it in 3D)
+        for st in ("f16dev",):
             L3 = make_droplet(ev, synth, shape, 40.0 * n / 256, 0.8, st)
             L3.step(cmp)
             r3, _, _ = L3.moments(device=True)

@@ -21,7 +21,7 @@
  *     alive for the duration of the call.  Host reads block until the data
  *     is on the host; everything else is enqueued on the handle's stream.
  *   - A handle is not thread-safe; separate handles are independent.
- *   - The periodic lattice is the only boundary condition.
+ *   - The lattice is periodic; evlbm_set_walls puts diffuse walls normal to x.
  */
 #ifndef EVLBM_H
 #define EVLBM_H
@@ -51,7 +51,11 @@ enum { EVLBM_D2Q9 = 2, EVLBM_D3Q27 = 3 };
  * (eq. feq, eq. geq with u = 0) of a per-cell reference state (rho_ref,
  * theta_ref), s = f^ref for f and (3/2) RT_ref f^ref for g.  The reference
  * state is set from the initial fields and, on a lattice, refreshed from the
- * stored state of every cell every EVLBM_OPT_REREF_EVERY steps (default 100). */
+ * stored state of every cell every EVLBM_OPT_REREF_EVERY steps (default 100).
+ * F16DEV keeps the density within 1e-3 of FP32 storage and of the FP64 oracle.
+ * BF16DEV (8-bit significand) is experimental: it misses that bar in 3D
+ * (about 1.3e-3 after 1e4 steps at 128^3, 3e-3 against the oracle after 1000
+ * steps on a small droplet). */
 enum { EVLBM_F64 = 0, EVLBM_F32 = 1, EVLBM_F16DEV = 2, EVLBM_BF16DEV = 3 };
 
 enum { EVLBM_HOST_F64 = 0, EVLBM_DEVICE_F32 = 1, EVLBM_DEVICE_F64 = 2 };
@@ -61,12 +65,21 @@ enum {
     EVLBM_OPT_CHECK_EVERY = 4, /* scan for non-finite densities every K steps (0 = never) */
     EVLBM_OPT_USE_GRAPH = 5,   /* 1: replay step chunks from a captured hipGraph (default 1) */
     EVLBM_OPT_REREF_EVERY = 6, /* 16-bit storage: re-reference every K steps (0 = never; default 100) */
+    EVLBM_OPT_EOS = 8,         /* contact factor of Enskog's pressure: EVLBM_EOS_VDW (default) or EVLBM_EOS_CS */
     EVLBM_OPT_PUSH_MOMENTS = 7 /* 1 = one-pass step (default), 0 = two-pass step, where the moments are pulled
                                   again before each collision.  D3Q27 with FP32 or FP64 storage: the collision
                                   pushes the next moments (16-bit D3Q27 storage is always two-pass).  D2Q9:
                                   the collision sums its tile's halo moments from the pulled populations;
                                   the result is bit for bit the two-pass step's */
 };
+
+/* Enskog's pressure P_E = rho R T (1 + b rho chi) with the contact value chi
+ * of the pair distribution (the text after eq. Ework): VDW chi = 1/(1 - b rho),
+ * i.e. P_E = rho R T/(1 - b rho), the paper's form; CS the Carnahan-Starling
+ * hard-sphere value chi = (1 - eta/2)/(1 - eta)^3 with eta = b rho/4.  Under
+ * the gauge P0 = P_E (eq. P0E) the closure enters theta = P0/rho and gamma_0
+ * of eq. gamma. */
+enum { EVLBM_EOS_VDW = 0, EVLBM_EOS_CS = 1 };
 
 enum { EVLBM_MEASURE_SLAB = 1, EVLBM_MEASURE_DROPLET = 2 };
 
@@ -90,9 +103,10 @@ int evlbm_create(int lattice, int nx, int ny, int nz, int storage, void *stream,
 /* Release every resource of the handle; NULL is accepted. */
 int evlbm_destroy(evlbm_t h);
 
-/* Equation of state: Enskog pressure P_E = rho R T/(1 - b rho), mean-field
- * pressure P_V = -a rho^2 and capillarity kappa (eq. EVforce1 and the text
- * after it).  a = b = kappa = 0 is the ideal gas.
+/* Equation of state: Enskog pressure P_E = rho R T/(1 - b rho) (or the
+ * Carnahan-Starling form, EVLBM_OPT_EOS), mean-field pressure P_V = -a rho^2
+ * and capillarity kappa (eq. EVforce1 and the text after it).
+ * a = b = kappa = 0 is the ideal gas.
  * Errors: EINVAL if R <= 0 or a, b, kappa < 0. */
 int evlbm_set_eos(evlbm_t h, double R, double a, double b, double kappa);
 
@@ -173,10 +187,38 @@ int evlbm_profile_step(evlbm_t h, int nsteps, double out[2]);
 /* Wait for all work enqueued on the handle's stream. */
 int evlbm_synchronize(evlbm_t h);
 
-/* van der Waals coexistence at temperature T: out = {rho_l, rho_v, P_coex}
- * (equal pressure and chemical potential, Newton iteration).  Used for the
- * initial profiles.  Errors: EINVAL if T is not below T_c = 8a/(27 b R). */
-int evlbm_eos_coexistence(double R, double a, double b, double T, double out[3]);
+/* Diffuse walls normal to x for the thermal Couette flow (the paragraph after
+ * eq. P0E, Fig. 2): a wall at rest half a cell before the first cell
+ * (x = -1/2) and one moving with U_wall along y half a cell after the last
+ * (x = nx - 1/2), both at temperature T_wall; y and z stay periodic.  The
+ * paper gives the wall values only; the scheme: a population entering a cell
+ * from a wall is the wall's equilibrium (eq. feq, eq. geq at the wall's
+ * velocity, R T_wall and theta = R T_wall Z(rho) at the cell's stored
+ * density) times the density that makes it carry the mass the cell's
+ * populations send into the wall in the same step (diffuse reflection:
+ * mass conserving); the finite-difference stencils take a field beyond a wall
+ * as the linear extrapolation through the two cells next to it.  enable = 0
+ * restores the periodic lattice.  FP64 and FP32 storage.  With walls the step
+ * takes four plain launches (pull with the walls, Laplacian, fields,
+ * collision); evlbm_read_moments, evlbm_global_sums and the checkpoints follow
+ * the walls; evlbm_measure and evlbm_profile_step return EINVAL.
+ * Errors: EINVAL (16-bit storage, nx < 2, T_wall <= 0, U_wall not finite),
+ * ENOMEM (work buffers: 2Q + 3D + 2 values per cell). */
+int evlbm_set_walls(evlbm_t h, int enable, double T_wall, double U_wall);
+
+/* Liquid-vapour coexistence of the bulk pressure P = P_E - a rho^2 of closure
+ * `eos` (EVLBM_EOS_*) at temperature T: out = {rho_l, rho_v, P_coex} (equal
+ * pressure and chemical potential, Newton iteration).  Used for the initial
+ * profiles.  Errors: EINVAL if eos is unknown, a or b <= 0, or T is not below
+ * T_c (evlbm_eos_critical). */
+int evlbm_eos_coexistence(int eos, double R, double a, double b, double T, double out[3]);
+
+/* Critical point of the bulk pressure P = P_E - a rho^2 of closure `eos`:
+ * out = {rho_c, T_c, P_c}.  van der Waals: 1/(3b), 8a/(27 b R), a/(27 b^2);
+ * Carnahan-Starling: eta_c = b rho_c/4 solves s'(eta) = eta s''(eta) for
+ * s = 4 eta Z(eta) (bisection), R T_c = 32 a/(b s''(eta_c)).
+ * Errors: EINVAL if eos is unknown or a, b <= 0. */
+int evlbm_eos_critical(int eos, double R, double a, double b, double out[3]);
 
 /* Attainable HBM bandwidth: a plain device-to-device streaming copy of
  * `bytes` total traffic (half read, half written), timed over `reps` launches
@@ -206,6 +248,10 @@ int evlbm_batch_destroy(evlbm_batch_t b);
 /* Shared parameters (as evlbm_set_eos, evlbm_set_relaxation, EVLBM_OPT_SPHI). */
 int evlbm_batch_set_params(evlbm_batch_t b, double R, double a, double bexcl, double kappa, double tau,
                            double lambda, double sphi);
+
+/* Batch options: EVLBM_OPT_SPHI, EVLBM_OPT_REREF_EVERY and EVLBM_OPT_EOS, as on a
+ * lattice, shared by every domain.  Errors: EINVAL (other keys, bad values). */
+int evlbm_batch_set_option(evlbm_batch_t b, int key, double value);
 
 /* Initialise domain k from host FP64 fields rho[N_k], u[2 N_k] (nullable), T[N_k].
  * With 16-bit storage the domain's per-cell reference state is taken from
@@ -271,15 +317,45 @@ int evlbm_mlp_get_hull(evlbm_mlp_t m, double out[4]);
 int evlbm_mlp_density_field(evlbm_mlp_t m, int nx, int ny, int nz, double cx, double cy, double cz, double R,
                             double Tr, double rho_c, double *rho_dev);
 
-/* Initialise a droplet of radius R centred at (cx, cy, cz) at T/Tc = Tr, at
- * rest: TANH = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh((r - R)/width) with
- * the coexistence densities; MLP = the network's profile, falling back to
- * TANH when (Tr, R) lies outside the network's trusted box
- * (evlbm_mlp_set_hull) or the radial profile is non-finite, increasing in r
- * or outside [0.5 rho_v, 1.2 rho_l].
- * *used_mlp (nullable) tells which was used.  Needs a > 0, b > 0. */
+/* ------------------------------------------------------------------------
+ * Initialisers of the workloads' synthetic states.  Each builds FP64 density
+ * and temperature fields on the device and calls evlbm_init_fields (f = f^eq,
+ * g = g^eq at rest, eq. feq and eq. geq).  Densities come from the handle's
+ * pressure closure: the coexistence densities rho_l, rho_v at T = Tr T_c
+ * (evlbm_eos_coexistence, evlbm_eos_critical), so a > 0 and b > 0 are needed.
+ * Seeded noise is multiplicative on the density, rho <- rho (1 + noise
+ * (2 u_c - 1)), with u_c the splitmix64 output (Steele, Lea & Flood, OOPSLA
+ * 2014) number c + 1 of the stream `seed`, c the cell's linear index
+ * x + nx (y + ny z), taken as a double in [0, 1) from its top 53 bits; noise 0
+ * adds none.  Synchronous.  Errors: EINVAL (bad geometry, Tr outside (0, 1),
+ * noise outside [0, 1), no two phases), ENOMEM, ENONPHYS, EHIP.
+ * ------------------------------------------------------------------------ */
+
+/* Flat liquid slab between x0 and x1 along x, uniform in y and z:
+ * rho = rho_v + (rho_l - rho_v)/2 [tanh((x - x0)/width) - tanh((x - x1)/width)],
+ * T = Tr T_c, at rest (the flat-interface workload of Fig. 1). */
+int evlbm_init_slab(evlbm_t h, double x0, double x1, double Tr, double width, uint64_t seed, double noise);
+
+/* Droplet of radius R centred at (cx, cy, cz) at T/Tc = Tr, at rest:
+ * TANH = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh((r - R)/width); MLP = the
+ * network's profile, falling back to TANH when (Tr, R) lies outside the
+ * network's trusted box (evlbm_mlp_set_hull) or the radial profile is
+ * non-finite, increasing in r or outside [0.5 rho_v, 1.2 rho_l].
+ * *used_mlp (nullable) tells which was used. */
 int evlbm_init_droplet(evlbm_t h, double cx, double cy, double cz, double R, double Tr, int profile, evlbm_mlp_t mlp,
-                       double width, int *used_mlp);
+                       double width, uint64_t seed, double noise, int *used_mlp);
+
+/* The droplet of evlbm_init_droplet carrying a given total mass and total
+ * energy (global sums 0 and 5 of another state, e.g. the plain run it is to
+ * meet: a periodic lattice conserves both, so two runs can only reach the
+ * same state from equal values).  The density profile is scaled to `mass`,
+ * and the uniform temperature T is found by Newton steps from Tr T_c with the
+ * slope d(sum 5)/dT = (3/2) R mass of a state at rest, until the energy agrees
+ * to 1e-13 relative (at most 8 steps); *T_used (nullable) receives it.
+ * Errors as above, ENONPHYS if the temperature comes out <= 0. */
+int evlbm_init_droplet_matched(evlbm_t h, double cx, double cy, double cz, double R, double Tr, int profile,
+                               evlbm_mlp_t mlp, double width, uint64_t seed, double noise, double mass,
+                               double energy, int *used_mlp, double *T_used);
 
 /* Build information: "gfx950 <storage variants> <date>" (static string). */
 const char *evlbm_version(void);

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libevlbm.so")
 D2Q9, D3Q27 = 2, 3
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 HOST_F64, DEVICE_F32, DEVICE_F64 = 0, 1, 2
-OPT_SPHI, OPT_CHECK_EVERY, OPT_USE_GRAPH, OPT_REREF_EVERY, OPT_PUSH_MOMENTS = 1, 4, 5, 6, 7
+OPT_SPHI, OPT_CHECK_EVERY, OPT_USE_GRAPH, OPT_REREF_EVERY, OPT_PUSH_MOMENTS, OPT_EOS = 1, 4, 5, 6, 7, 8
+EOS = {"vdw": 0, "cs": 1}  # contact factor of Enskog's pressure: van der Waals, Carnahan-Starling
 MEASURE_SLAB, MEASURE_DROPLET = 1, 2
 STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE", -6: "EIO", -7: "ENONPHYS"}
@@ -68,11 +69,13 @@ def lib():
         L.evlbm_checkpoint_load.argtypes = [_vp, ctypes.c_char_p]
         L.evlbm_synchronize.argtypes = [_vp]
         L.evlbm_profile_step.argtypes = [_vp, ctypes.c_int, _dp]
-        L.evlbm_eos_coexistence.argtypes = [ctypes.c_double] * 4 + [_dp]
+        L.evlbm_eos_coexistence.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [_dp]
+        L.evlbm_eos_critical.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3 + [_dp]
         L.evlbm_copy_probe.argtypes = [ctypes.c_double, ctypes.c_int, _dp]
         L.evlbm_batch_create.argtypes = [ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.POINTER(_vp)]
         L.evlbm_batch_destroy.argtypes = [_vp]
         L.evlbm_batch_set_params.argtypes = [_vp] + [ctypes.c_double] * 7
+        L.evlbm_batch_set_option.argtypes = [_vp, ctypes.c_int, ctypes.c_double]
         L.evlbm_batch_init_domain.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
         L.evlbm_batch_step.argtypes = [_vp, ctypes.c_int64]
         L.evlbm_batch_read.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
@@ -89,8 +92,14 @@ def lib():
         L.evlbm_mlp_train.argtypes = [_vp, _fp, _fp, ctypes.c_int, ctypes.c_int, ctypes.c_float, _fp]
         L.evlbm_mlp_set_hull.argtypes = [_vp] + [ctypes.c_double] * 4
         L.evlbm_mlp_get_hull.argtypes = [_vp, _dp]
-        L.evlbm_init_droplet.argtypes = [_vp] + [ctypes.c_double] * 5 + [ctypes.c_int, _vp, ctypes.c_double,
-                                                                         ctypes.POINTER(ctypes.c_int)]
+        L.evlbm_init_droplet.argtypes = ([_vp] + [ctypes.c_double] * 5 + [ctypes.c_int, _vp, ctypes.c_double,
+                                         ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(ctypes.c_int)])
+        L.evlbm_init_slab.argtypes = [_vp] + [ctypes.c_double] * 4 + [ctypes.c_uint64, ctypes.c_double]
+        L.evlbm_init_droplet_matched.argtypes = ([_vp] + [ctypes.c_double] * 5 + [ctypes.c_int, _vp, ctypes.c_double,
+                                                 ctypes.c_uint64] + [ctypes.c_double] * 3 +
+                                                 [ctypes.POINTER(ctypes.c_int), _dp])
+        L.evlbm_mlp_density_field.argtypes = [_vp] + [ctypes.c_int] * 3 + [ctypes.c_double] * 6 + [_vp]
+        L.evlbm_set_walls.argtypes = [_vp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
         L.evlbm_batch_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)] + [ctypes.POINTER(ctypes.c_int)] * 4
         _lib = L
     return _lib
@@ -113,10 +122,18 @@ def _ptr(a):
     return ctypes.c_void_p(a.data_ptr())  # torch tensor
 
 
-def eos_coexistence(T, R=1.0, a=0.0225, b=1.0 / 3.0):
-    """(rho_l, rho_v, P_coex) of the van der Waals equation at temperature T."""
+def eos_coexistence(T, R=1.0, a=0.0225, b=1.0 / 3.0, eos="vdw"):
+    """(rho_l, rho_v, P_coex) of the bulk pressure P_E - a rho^2 at temperature T
+    (eos: "vdw" or "cs")."""
     out = np.zeros(3)
-    _check(lib().evlbm_eos_coexistence(R, a, b, T, out.ctypes.data_as(_dp)))
+    _check(lib().evlbm_eos_coexistence(EOS[eos], R, a, b, T, out.ctypes.data_as(_dp)))
+    return tuple(out)
+
+
+def eos_critical(R=1.0, a=0.0225, b=1.0 / 3.0, eos="vdw"):
+    """(rho_c, T_c, P_c) of the bulk pressure P_E - a rho^2 (eos: "vdw" or "cs")."""
+    out = np.zeros(3)
+    _check(lib().evlbm_eos_critical(EOS[eos], R, a, b, out.ctypes.data_as(_dp)))
     return tuple(out)
 
 
@@ -169,13 +186,19 @@ class Lattice:
     def set_relaxation(self, tau=1.0, lam=1.0):
         _check(lib().evlbm_set_relaxation(self._h, tau, lam))
 
-    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0):
+    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0, eos="vdw"):
         self.set_eos(R, a, b, kappa)
         self.set_relaxation(tau, lam)
         self.set_option(OPT_SPHI, sphi)
+        self.set_option(OPT_EOS, EOS[eos])
 
     def set_option(self, key, value):
         _check(lib().evlbm_set_option(self._h, int(key), float(value)))
+
+    def set_walls(self, Tw, Uw, enable=True):
+        """Diffuse walls normal to x: at rest at x = -1/2, moving with Uw along
+        y at x = nx - 1/2, both at temperature Tw (evlbm_set_walls)."""
+        _check(lib().evlbm_set_walls(self._h, 1 if enable else 0, float(Tw), float(Uw)))
 
     # -- state
     def init_fields(self, rho, T, u=None):
@@ -269,18 +292,42 @@ class Lattice:
         assert f.size == self.Q * self.N and g.size == self.Q * self.N
         _check(lib().evlbm_set_populations(self._h, _ptr(f), _ptr(g), HOST_F64))
 
-    def init_droplet(self, radius, Tr, profile="tanh", mlp=None, centre=None, width=2.0):
-        """Droplet at rest at T/Tc = Tr: tanh profile between the coexistence
-        densities, or the network's profile (with the tanh fallback).  Returns
-        True when the network's profile was used."""
+    def _centre(self, centre):
         if centre is None:
             centre = ((self.nx - 1) / 2.0, (self.ny - 1) / 2.0, (self.nz - 1) / 2.0)
+        return [float(v) for v in list(centre) + [0.0] * (3 - len(centre))]
+
+    def init_droplet(self, radius, Tr, profile="tanh", mlp=None, centre=None, width=2.0, seed=0, noise=0.0):
+        """Droplet at rest at T/Tc = Tr: tanh profile between the coexistence
+        densities, or the network's profile (with the tanh fallback), with
+        seeded multiplicative noise.  Returns True when the network's profile
+        was used."""
         used = ctypes.c_int()
-        prof = 1 if profile == "mlp" else 0
-        _check(lib().evlbm_init_droplet(self._h, float(centre[0]), float(centre[1]), float(centre[2]), float(radius),
-                                        float(Tr), prof, None if mlp is None else mlp._h, float(width),
-                                        ctypes.byref(used)))
+        c = self._centre(centre)
+        _check(lib().evlbm_init_droplet(self._h, c[0], c[1], c[2], float(radius), float(Tr),
+                                        1 if profile == "mlp" else 0, None if mlp is None else mlp._h, float(width),
+                                        int(seed), float(noise), ctypes.byref(used)))
         return bool(used.value)
+
+    def init_droplet_matched(self, radius, Tr, mass, energy, profile="mlp", mlp=None, centre=None, width=2.0,
+                             seed=0, noise=0.0):
+        """The droplet of init_droplet carrying total mass `mass` and total
+        energy `energy` (global sums 0 and 5).  Returns (network used, T)."""
+        used = ctypes.c_int()
+        T = ctypes.c_double()
+        c = self._centre(centre)
+        _check(lib().evlbm_init_droplet_matched(self._h, c[0], c[1], c[2], float(radius), float(Tr),
+                                                1 if profile == "mlp" else 0, None if mlp is None else mlp._h,
+                                                float(width), int(seed), float(noise), float(mass), float(energy),
+                                                ctypes.byref(used), ctypes.byref(T)))
+        return bool(used.value), T.value
+
+    def init_slab(self, Tr, x0=None, x1=None, width=2.0, seed=0, noise=0.0):
+        """Flat liquid slab between x0 and x1 (default nx/4 and 3 nx/4) at rest
+        at T/Tc = Tr, with seeded multiplicative noise."""
+        x0 = self.nx / 4.0 if x0 is None else x0
+        x1 = 3.0 * self.nx / 4.0 if x1 is None else x1
+        _check(lib().evlbm_init_slab(self._h, float(x0), float(x1), float(Tr), float(width), int(seed), float(noise)))
 
     def checkpoint_save(self, path):
         _check(lib().evlbm_checkpoint_save(self._h, str(path).encode()))
@@ -318,8 +365,9 @@ class Batch:
             _lib.evlbm_batch_destroy(h)
             self._h = None
 
-    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0):
+    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0, eos="vdw"):
         _check(lib().evlbm_batch_set_params(self._h, R, a, b, kappa, tau, lam, sphi))
+        _check(lib().evlbm_batch_set_option(self._h, OPT_EOS, float(EOS[eos])))
 
     def init_domain(self, k, rho, T, u=None):
         nx, ny = self.sizes[k]
@@ -445,6 +493,19 @@ class MLP:
         loss = np.zeros(1, dtype=np.float32)
         _check(lib().evlbm_mlp_grad(self._h, _fptr(X), _fptr(Y), X.shape[0], _fptr(g), _fptr(loss)))
         return g, float(loss[0])
+
+    def density_field(self, shape, centre, radius, Tr, rho_c=1.0):
+        """Device FP64 field rho_c y(T/Tc, R, |x - c|/R) on a [nz, ny, nx]
+        lattice (a torch tensor; nz = 1: 2D distance)."""
+        import torch
+        nz, ny, nx = shape
+        c = list(centre) + [0.0] * (3 - len(centre))
+        with torch.cuda.stream(self.stream):
+            out = torch.empty(shape, dtype=torch.float64, device="cuda")
+        _check(lib().evlbm_mlp_density_field(self._h, nx, ny, nz, float(c[0]), float(c[1]), float(c[2]),
+                                             float(radius), float(Tr), float(rho_c), _ptr(out)))
+        torch.cuda.current_stream().wait_stream(self.stream)
+        return out
 
     def train(self, X, Y, iters, lr=1e-3):
         X, Y = _f32(X).reshape(-1, 3), _f32(Y)

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libevlbm.so")
-SOURCES = ["evlbm_lattice.hip", "evlbm_batch.hip", "evlbm_mlp.hip"]
+SOURCES = ["evlbm_lattice.hip", "evlbm_batch.hip", "evlbm_mlp.hip", "evlbm_init.hip", "evlbm_walls.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -101,6 +101,7 @@ struct evlbm_batch {
     int grid[NVARIANT][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // persistent grid: moments, collide
     int variant = 0;
     double R = 1.0, a = 0.0, b = 0.0, kappa = 0.0, tau = 1.0, lambda = 1.0, sphi = -1.0;
+    int eos = EVLBM_EOS_VDW;
     int cur = 0;
     int64_t step = 0;
     int64_t reref_every = 100;  // 16-bit storage: re-reference period in steps (as a lattice's default)
@@ -137,7 +138,7 @@ int scratch(evlbm_batch *b, size_t bytes)
 template <typename R>
 StepParams<R> bparams(const evlbm_batch *b)
 {
-    StepParams<R> p = model_params<R>(b->R, b->a, b->b, b->kappa, b->tau, b->lambda, b->sphi);
+    StepParams<R> p = model_params<R>(b->eos, b->R, b->a, b->b, b->kappa, b->tau, b->lambda, b->sphi);
     p.refst = b->refst;
     return p;
 }
@@ -399,14 +400,39 @@ int evlbm_batch_set_params(evlbm_batch_t b, double R, double a, double bb, doubl
     return EVLBM_OK;
 }
 
+int evlbm_batch_set_option(evlbm_batch_t b, int key, double value)
+{
+    if (!b) return fail(EVLBM_EINVAL, "null batch");
+    switch (key) {
+    case EVLBM_OPT_SPHI:
+        if (value != 1.0 && value != -1.0 && value != 0.0) return fail(EVLBM_EINVAL, "s_phi must be -1, 0 or +1");
+        b->sphi = value;
+        break;
+    case EVLBM_OPT_REREF_EVERY:
+        if (value < 0) return fail(EVLBM_EINVAL, "re-reference period must be >= 0");
+        b->reref_every = (int64_t)value;
+        break;
+    case EVLBM_OPT_EOS:
+        if (value != EVLBM_EOS_VDW && value != EVLBM_EOS_CS) return fail(EVLBM_EINVAL, "unknown pressure closure");
+        b->eos = (int)value;
+        break;
+    default:
+        return fail(EVLBM_EINVAL, "option %d is not a batch option", key);
+    }
+    drop_graphs(b);
+    return EVLBM_OK;
+}
+
 int evlbm_batch_init_domain(evlbm_batch_t b, int k, const double *rho, const double *u, const double *T)
 {
     if (!b || k < 0 || k >= b->n || !rho || !T) return fail(EVLBM_EINVAL, "bad domain index or null field");
     const DomainRec &d = b->doms[k];
     for (long c = 0; c < d.N; ++c) {
         if (!std::isfinite(rho[c]) || !std::isfinite(T[c])) return fail(EVLBM_ENONFINITE, "non-finite field");
-        if (!(rho[c] > 0) || !(1.0 - b->b * rho[c] > 0) || !(T[c] > 0))
-            return fail(EVLBM_ENONPHYS, "domain %d cell %ld: need rho > 0, b rho < 1, T > 0", k, c);
+        double Z;
+        if (!(rho[c] > 0) || !enskog_z64(b->eos, b->b, rho[c], &Z) || !(T[c] > 0))
+            return fail(EVLBM_ENONPHYS, "domain %d cell %ld: need rho > 0 inside the pressure closure's range, T > 0",
+                        k, c);
     }
     int rc = scratch(b, sizeof(double) * d.N * 4);
     if (rc) return rc;
@@ -417,7 +443,7 @@ int evlbm_batch_init_domain(evlbm_batch_t b, int k, const double *rho, const dou
     if (e != hipSuccess) return hip_fail(e, "copying initial fields");
     if (b->refst)
         hipLaunchKernelGGL(k_ref_from_fields<2>, dim3((d.N + 255) / 256), dim3(256), 0, b->stream, (const double *)dr,
-                           (const double *)dt, d.N, b->R, b->b, b->refst + d.cell_off);
+                           (const double *)dt, d.N, b->R, b->eos, b->b, b->refst + d.cell_off);
     BATCH_DISPATCH(init(b, k, dr, du, dt));
     e = hipStreamSynchronize(b->stream);
     if (e == hipSuccess) e = hipGetLastError();

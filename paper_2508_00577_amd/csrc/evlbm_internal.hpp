@@ -23,6 +23,13 @@ struct evlbm_lattice {
     size_t scratch_bytes = 0;
     // model
     double R = 1.0, a = 0.0, b = 0.0, kappa = 0.0, tau = 1.0, lambda = 1.0, sphi = -1.0;
+    int eos = EVLBM_EOS_VDW;
+    // diffuse walls normal to x (evlbm_set_walls): temperature, speed of the
+    // wall at x = nx - 1/2, work buffers of the wall step (streamed
+    // populations [2Q][N], fields [3D + 2][N], arithmetic precision)
+    bool walls = false;
+    double Tw = 0.0, Uw = 0.0;
+    void *wall_fh = nullptr, *wall_fld = nullptr;
     int64_t check_every = 0;
     int64_t reref_every = 100;           // 16-bit storage: re-reference period (0 = never)
     bool use_graph = true;
@@ -45,7 +52,12 @@ int run_steps(evlbm_lattice *h, int64_t n);
 int scan_nonfinite(evlbm_lattice *h);
 int rereference(evlbm_lattice *h);
 size_t store_bytes(int storage);
+hipStream_t mlp_stream(evlbm_mlp_t m);  // the stream a network's kernels run on
+// the wall step and its readouts (evlbm_walls.hip)
+void wall_step(evlbm_lattice *h);
+void wall_analyse(evlbm_lattice *h);
+int wall_read_moments(evlbm_lattice *h, void *rho, void *u, void *T, int where, double *host_scratch);
+void wall_sums(evlbm_lattice *h, double *partial);
 size_t real_bytes(int storage);
-void reference_populations(int D, double R, double b, double rho, double T, double out[54]);
 
 }  // namespace evlbm

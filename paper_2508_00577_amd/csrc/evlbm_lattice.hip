@@ -45,7 +45,7 @@ size_t real_bytes(int storage) { return storage == EVLBM_F64 ? 8 : 4; }
 template <typename R>
 StepParams<R> make_params(const evlbm_lattice *h)
 {
-    StepParams<R> p = model_params<R>(h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi);
+    StepParams<R> p = model_params<R>(h->eos, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi);
     p.nx = h->nx;
     p.ny = h->ny;
     p.nz = h->nz;
@@ -169,7 +169,7 @@ struct Ops {
     static void measure(evlbm_lattice *h, int kind, const double *g, double *partial, long nb)
     {
         hipLaunchKernelGGL((k_measure<D, R>), dim3(nb), dim3(256), 0, h->stream, (const R *)h->m, (const R *)h->lap,
-                           h->nx, h->ny, h->nz, (R)h->a, (R)h->b, (R)h->kappa, (R)h->R, kind, g[0], g[1], g[2], g[3],
+                           h->nx, h->ny, h->nz, h->eos, (R)h->a, (R)h->b, (R)h->kappa, (R)h->R, kind, g[0], g[1], g[2], g[3],
                            g[4], g[5], partial);
     }
     static void decode(evlbm_lattice *h, double *out)
@@ -193,7 +193,7 @@ struct Ops {
     static void ref_from_pops(evlbm_lattice *h, const double *pops)
     {
         hipLaunchKernelGGL((k_ref_from_pops<D>), dim3((h->N + 255) / 256), dim3(256), 0, h->stream, pops, h->N,
-                           h->b, h->refst);
+                           h->eos, h->b, h->refst);
     }
     static void scan(evlbm_lattice *h, int *flag)
     {
@@ -296,9 +296,15 @@ int ensure_scratch(evlbm_lattice *h, size_t bytes)
     return EVLBM_OK;
 }
 
-// Make sure h->m holds the pulled moments of the current buffer.
+// Make sure h->m holds the pulled moments of the current buffer (with walls:
+// always pulled again, with the walls' re-emission).
 void refresh_moments(evlbm_lattice *h)
 {
+    if (h->walls) {
+        wall_analyse(h);
+        h->m_valid = false;
+        return;
+    }
     if (!h->m_valid) {
         dispatch<RunMoments>(h, (const void *)h->buf[h->cur]);
         h->m_valid = true;
@@ -352,15 +358,23 @@ int scan_nonfinite(evlbm_lattice *h)
 }
 
 // Does the step push the next moments (D3Q27 one-pass step)?
-static bool pushes(const evlbm_lattice *h) { return h->D == 3 && h->push && h->shell != nullptr; }
+static bool pushes(const evlbm_lattice *h) { return h->D == 3 && h->push && h->shell != nullptr && !h->walls; }
 // the one-pass D2Q9 step: the collision sums its halo's moments itself
-static bool fused(const evlbm_lattice *h) { return h->D == 2 && h->push; }
+static bool fused(const evlbm_lattice *h) { return h->D == 2 && h->push && !h->walls; }
 
 // One step: moments of the current buffer, collision into the other.  The
 // one-pass D3Q27 step also leaves the moments of the new state in m_alt,
 // which becomes m; the one-pass D2Q9 step needs no moments.
 void launch_step(evlbm_lattice *h, hipEvent_t between)
 {
+    if (h->walls) {
+        if (between) (void)hipEventRecord(between, h->stream);
+        wall_step(h);
+        h->m_valid = false;
+        h->cur = 1 - h->cur;
+        h->step++;
+        return;
+    }
     if (!fused(h)) refresh_moments(h);
     const int nxt = 1 - h->cur;
     if (pushes(h)) {
@@ -514,6 +528,8 @@ int evlbm_destroy(evlbm_t h)
     if (h->m_alt) hipFree(h->m_alt);
     if (h->shell) hipFree(h->shell);
     if (h->lap) hipFree(h->lap);
+    if (h->wall_fh) (void)hipFree(h->wall_fh);
+    if (h->wall_fld) (void)hipFree(h->wall_fld);
     if (h->refst) hipFree(h->refst);
     if (h->scratch) hipFree(h->scratch);
     delete h;
@@ -575,6 +591,10 @@ int evlbm_set_option(evlbm_t h, int key, double value)
         h->push = value != 0.0;
         h->m_valid = false;
         break;
+    case EVLBM_OPT_EOS:
+        if (value != EVLBM_EOS_VDW && value != EVLBM_EOS_CS) return fail(EVLBM_EINVAL, "unknown pressure closure");
+        h->eos = (int)value;
+        break;
     default:
         return fail(EVLBM_EINVAL, "unknown option %d", key);
     }
@@ -602,8 +622,9 @@ int evlbm_init_fields(evlbm_t h, const void *rho, const void *u, const void *T, 
         for (long c = 0; c < N; ++c) {
             if (!std::isfinite(hr[c]) || !std::isfinite(ht[c]))
                 return fail(EVLBM_ENONFINITE, "non-finite initial field at cell %ld", c);
-            if (!(hr[c] > 0) || !(1.0 - h->b * hr[c] > 0) || !(ht[c] > 0))
-                return fail(EVLBM_ENONPHYS, "cell %ld: need rho > 0, b rho < 1, T > 0", c);
+            double Z;
+            if (!(hr[c] > 0) || !enskog_z64(h->eos, h->b, hr[c], &Z) || !(ht[c] > 0))
+                return fail(EVLBM_ENONPHYS, "cell %ld: need rho > 0 inside the pressure closure's range, T > 0", c);
         }
         e = hipMemcpyAsync(d_rho, rho, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(d_T, T, sizeof(double) * N, hipMemcpyHostToDevice, h->stream);
@@ -627,21 +648,22 @@ int evlbm_init_fields(evlbm_t h, const void *rho, const void *u, const void *T, 
         int zero = 0, host = 0;
         e = hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, h->stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-        hipLaunchKernelGGL(k_validate, dim3((N + 255) / 256), dim3(256), 0, h->stream, d_rho, d_T, N, h->b, flag);
+        hipLaunchKernelGGL(k_validate, dim3((N + 255) / 256), dim3(256), 0, h->stream, d_rho, d_T, N, h->eos, h->b,
+                           flag);
         e = hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return hip_fail(e, "validating initial fields");
         if (host & 2) return fail(EVLBM_ENONFINITE, "non-finite initial field");
-        if (host & 1) return fail(EVLBM_ENONPHYS, "need rho > 0, b rho < 1, T > 0 everywhere");
+        if (host & 1) return fail(EVLBM_ENONPHYS, "need rho > 0 inside the pressure closure's range, T > 0 everywhere");
     }
     h->cur = 0;
     if (h->refst) {
         if (h->D == 2)
             hipLaunchKernelGGL(k_ref_from_fields<2>, dim3((N + 255) / 256), dim3(256), 0, h->stream,
-                               (const double *)d_rho, (const double *)d_T, N, h->R, h->b, h->refst);
+                               (const double *)d_rho, (const double *)d_T, N, h->R, h->eos, h->b, h->refst);
         else
             hipLaunchKernelGGL(k_ref_from_fields<3>, dim3((N + 255) / 256), dim3(256), 0, h->stream,
-                               (const double *)d_rho, (const double *)d_T, N, h->R, h->b, h->refst);
+                               (const double *)d_rho, (const double *)d_T, N, h->R, h->eos, h->b, h->refst);
     }
     dispatch<RunInit>(h, (const double *)d_rho, (const double *)d_u, (const double *)d_T);
     rc = check_launch("k_init");
@@ -695,9 +717,23 @@ int evlbm_read_moments(evlbm_t h, void *rho, void *u, void *T, int where)
     if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
     if (where != EVLBM_HOST_F64 && where != EVLBM_DEVICE_F32 && where != EVLBM_DEVICE_F64)
         return fail(EVLBM_EINVAL, "unknown location %d", where);
+    const long N = h->N;
+    if (h->walls) {
+        int rc = where == EVLBM_HOST_F64 ? ensure_scratch(h, sizeof(double) * N * (2 + h->D)) : EVLBM_OK;
+        if (rc == EVLBM_OK) rc = wall_read_moments(h, rho, u, T, where, (double *)h->scratch);
+        if (rc || where != EVLBM_HOST_F64) return rc;
+        const double *d = (const double *)h->scratch;
+        hipError_t e = hipSuccess;
+        if (rho) e = hipMemcpyAsync(rho, d, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && T) e = hipMemcpyAsync(T, d + N, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess && u)
+            e = hipMemcpyAsync(u, d + 2 * N, sizeof(double) * N * h->D, hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(e, "copying moments to the host");
+        return EVLBM_OK;
+    }
     refresh_moments(h);
     dispatch<RunLap>(h);
-    const long N = h->N;
     if (where == EVLBM_DEVICE_F32) {
         dispatch<RunReadoutF>(h, (float *)rho, (float *)u, (float *)T);
         return check_launch("readout");
@@ -725,12 +761,16 @@ int evlbm_global_sums(evlbm_t h, double out[8])
 {
     if (!h || !out) return fail(EVLBM_EINVAL, "null argument");
     if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
-    refresh_moments(h);
-    dispatch<RunLap>(h);
     const long nb = (h->N + 255) / 256;
     int rc = ensure_scratch(h, sizeof(double) * (nb * 9 + 16));
     if (rc) return rc;
-    dispatch<RunSums>(h, (double *)h->scratch, nb);
+    if (h->walls) {
+        wall_sums(h, (double *)h->scratch);
+    } else {
+        refresh_moments(h);
+        dispatch<RunLap>(h);
+        dispatch<RunSums>(h, (double *)h->scratch, nb);
+    }
     rc = check_launch("k_sums");
     if (rc) return rc;
     const int ops[8] = {0, 0, 0, 0, 0, 0, 1, 2};
@@ -742,6 +782,7 @@ int evlbm_measure(evlbm_t h, int kind, const double *geom, double out[8])
     if (!h || !geom || !out) return fail(EVLBM_EINVAL, "null argument");
     if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
     if (kind != EVLBM_MEASURE_SLAB && kind != EVLBM_MEASURE_DROPLET) return fail(EVLBM_EINVAL, "unknown kind %d", kind);
+    if (h->walls) return fail(EVLBM_EINVAL, "the region measurement is for periodic lattices (walls are set)");
     refresh_moments(h);
     dispatch<RunLap>(h);
     const long nb = (h->N + 255) / 256;
@@ -839,11 +880,12 @@ int evlbm_checkpoint_save(evlbm_t h, const char *path)
     if (!fp) return fail(EVLBM_EIO, "cannot open %s", path);
     char hdr[512];
     int n = snprintf(hdr, sizeof(hdr),
-                     "{\"format\":\"evlbm-4\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "{\"format\":\"evlbm-5\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%.17g,\"a\":%.17g,\"b\":%.17g,\"kappa\":%.17g,\"tau\":%.17g,\"lambda\":%.17g,"
-                     "\"sphi\":%.17g,\"step\":%lld,\"bytes\":%zu,\"moment_bytes\":%zu}\n",
+                     "\"sphi\":%.17g,\"eos\":%d,\"walls\":%d,\"Tw\":%.17g,\"Uw\":%.17g,\"step\":%lld,"
+                     "\"bytes\":%zu,\"moment_bytes\":%zu}\n",
                      h->D, h->nx, h->ny, h->nz, h->storage, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi,
-                     (long long)h->step, bytes, m_bytes);
+                     h->eos, h->walls ? 1 : 0, h->Tw, h->Uw, (long long)h->step, bytes, m_bytes);
     bool ok = fwrite(hdr, 1, n, fp) == (size_t)n && fwrite(host.data(), 1, bytes, fp) == bytes;
     if (ok && h->refst) {  // the 16-bit reference state of every cell
         std::vector<float4> r((size_t)h->N);
@@ -866,16 +908,19 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
         fclose(fp);
         return fail(EVLBM_EIO, "empty checkpoint %s", path);
     }
-    int D = 0, nx = 0, ny = 0, nz = 0, st = -1;
+    int D = 0, nx = 0, ny = 0, nz = 0, st = -1, eos = 0, walls = 0;
+    double Tw = 0.0, Uw = 0.0;
     long long step = 0;
     double R, a, b, kappa, tau, lam, sphi;
     size_t bytes = 0, m_bytes = 0;
     int got = sscanf(hdr,
-                     "{\"format\":\"evlbm-4\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
+                     "{\"format\":\"evlbm-5\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%lg,\"a\":%lg,\"b\":%lg,\"kappa\":%lg,\"tau\":%lg,\"lambda\":%lg,"
-                     "\"sphi\":%lg,\"step\":%lld,\"bytes\":%zu,\"moment_bytes\":%zu}",
-                     &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &step, &bytes, &m_bytes);
-    if (got != 15) {
+                     "\"sphi\":%lg,\"eos\":%d,\"walls\":%d,\"Tw\":%lg,\"Uw\":%lg,\"step\":%lld,"
+                     "\"bytes\":%zu,\"moment_bytes\":%zu}",
+                     &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &eos, &walls, &Tw, &Uw, &step, &bytes,
+                     &m_bytes);
+    if (got != 19 || (eos != EVLBM_EOS_VDW && eos != EVLBM_EOS_CS)) {
         fclose(fp);
         return fail(EVLBM_EIO, "bad checkpoint header in %s", path);
     }
@@ -915,6 +960,13 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
     h->tau = tau;
     h->lambda = lam;
     h->sphi = sphi;
+    h->eos = eos;
+    if (walls) {
+        const int rcw = evlbm_set_walls(h, 1, Tw, Uw);
+        if (rcw) return rcw;
+    } else {
+        h->walls = false;
+    }
     h->cur = 0;
     hipError_t e =
         hipMemcpy2D(h->buf[0], (size_t)h->ds * es, host.data(), row, row, 2 * h->Q, hipMemcpyHostToDevice);
@@ -936,6 +988,7 @@ int evlbm_profile_step(evlbm_t h, int nsteps, double out[2])
 {
     if (!h || !out || nsteps <= 0 || nsteps > 4096) return fail(EVLBM_EINVAL, "need 0 < nsteps <= 4096");
     if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
+    if (h->walls) return fail(EVLBM_EINVAL, "kernel profiling is for periodic lattices (walls are set)");
     std::vector<hipEvent_t> ev((size_t)3 * nsteps, nullptr);
     hipError_t e = hipSuccess;
     for (auto &x : ev)
@@ -980,32 +1033,131 @@ int evlbm_synchronize(evlbm_t h)
     return EVLBM_OK;
 }
 
-int evlbm_eos_coexistence(double R, double a, double b, double T, double out[3])
-{
-    if (!out || !(R > 0) || !(a > 0) || !(b > 0)) return fail(EVLBM_EINVAL, "need R, a, b > 0");
-    const double Tc = 8.0 * a / (27.0 * b * R);
-    if (!(T > 0) || !(T < Tc)) return fail(EVLBM_EINVAL, "T must lie in (0, T_c)");
-    const double RT = R * T, rc = 1.0 / (3.0 * b), s = std::sqrt(1.0 - T / Tc);
-    auto P = [&](double r) { return r * RT / (1.0 - b * r) - a * r * r; };
-    auto dP = [&](double r) { return RT / ((1.0 - b * r) * (1.0 - b * r)) - 2.0 * a * r; };
-    auto mu = [&](double r) { return RT * std::log(r / (1.0 - b * r)) + RT / (1.0 - b * r) - 2.0 * a * r; };
-    // start from the mean-field critical law and keep the iterates on their branches
-    double rl = std::fmin(rc * (1.0 + 2.0 * s), 0.98 / b), rv = std::fmax(rc * (1.0 - 2.0 * s), 1e-3 * rc);
-    for (int it = 0; it < 200; ++it) {
-        const double f1 = P(rl) - P(rv), f2 = mu(rl) - mu(rv);
-        const double a11 = dP(rl), a12 = -dP(rv), a21 = dP(rl) / rl, a22 = -dP(rv) / rv;
-        const double det = a11 * a22 - a12 * a21;
-        double drl = -(f1 * a22 - a12 * f2) / det, drv = -(a11 * f2 - a21 * f1) / det;
-        double t = 1.0;
-        while ((rl + t * drl >= 1.0 / b || rl + t * drl <= rc || rv + t * drv <= 0.0 || rv + t * drv >= rc) && t > 1e-6)
-            t *= 0.5;
-        rl += t * drl;
-        rv += t * drv;
-        if (std::fabs(drl) < 1e-15 * rl && std::fabs(drv) < 1e-15 * rv) break;
+namespace {
+
+// Host thermodynamics of the bulk pressure P = rho RT Z(rho) - a rho^2 of a
+// pressure closure (enskog_z64): P, dP/drho = RT (Z + rho Z') - 2 a rho and
+// the chemical potential mu = RT [ln rho + f_ex/RT + Z - 1] - 2 a rho (up to a
+// T-only constant; f_ex the hard-core excess free energy per particle):
+//   van der Waals: Z + rho Z' = 1/(1 - b rho)^2, f_ex/RT = -ln(1 - b rho);
+//   Carnahan-Starling (eta = b rho/4): Z + rho Z' = (1 + 4 eta + 4 eta^2 -
+//     4 eta^3 + eta^4)/(1 - eta)^4, f_ex/RT + Z - 1 = (8 eta - 9 eta^2 +
+//     3 eta^3)/(1 - eta)^3.
+struct HostEos {
+    int eos;
+    double RT, a, b;
+    double rmax() const { return eos == EVLBM_EOS_CS ? 4.0 / b : 1.0 / b; }
+    double P(double r) const
+    {
+        double Z = 0.0;
+        enskog_z64(eos, b, r, &Z);
+        return r * RT * Z - a * r * r;
     }
+    double dP(double r) const
+    {
+        if (eos == EVLBM_EOS_CS) {
+            const double e = 0.25 * b * r, o = 1.0 - e;
+            return RT * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (o * o * o * o) - 2.0 * a * r;
+        }
+        return RT / ((1.0 - b * r) * (1.0 - b * r)) - 2.0 * a * r;
+    }
+    double mu(double r) const
+    {
+        if (eos == EVLBM_EOS_CS) {
+            const double e = 0.25 * b * r, o = 1.0 - e;
+            return RT * (std::log(r) + e * (8.0 + e * (-9.0 + 3.0 * e)) / (o * o * o)) - 2.0 * a * r;
+        }
+        return RT * std::log(r / (1.0 - b * r)) + RT / (1.0 - b * r) - 2.0 * a * r;
+    }
+};
+
+// Critical point {rho_c, T_c, P_c}: closed form (van der Waals) or the
+// bisection of s'(eta) = eta s''(eta) for s = 4 eta Z (Carnahan-Starling) with
+// s' = 4 (1 + 4 eta + 4 eta^2 - 4 eta^3 + eta^4)/(1 - eta)^4 and
+// s'' = 16 (2 + 5 eta - eta^2)/(1 - eta)^5, then R T_c = 32 a/(b s''(eta_c)).
+void critical(int eos, double R, double a, double b, double out[3])
+{
+    if (eos == EVLBM_EOS_CS) {
+        auto s1 = [](double e) {
+            const double o = 1.0 - e;
+            return 4.0 * (1.0 + e * (4.0 + e * (4.0 + e * (-4.0 + e)))) / (o * o * o * o);
+        };
+        auto s2 = [](double e) {
+            const double o = 1.0 - e;
+            return 16.0 * (2.0 + e * (5.0 - e)) / (o * o * o * o * o);
+        };
+        double lo = 0.01, hi = 0.5;  // s' - eta s'' changes sign once in between
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if ((s1(mid) - mid * s2(mid)) > 0.0) lo = mid;
+            else hi = mid;
+        }
+        const double ec = 0.5 * (lo + hi), RTc = 32.0 * a / (b * s2(ec)), rc = 4.0 * ec / b;
+        const HostEos th{eos, RTc, a, b};
+        out[0] = rc;
+        out[1] = RTc / R;
+        out[2] = th.P(rc);
+        return;
+    }
+    out[0] = 1.0 / (3.0 * b);
+    out[1] = 8.0 * a / (27.0 * b * R);
+    out[2] = a / (27.0 * b * b);
+}
+
+}  // namespace
+
+int evlbm_eos_critical(int eos, double R, double a, double b, double out[3])
+{
+    if (!out || (eos != EVLBM_EOS_VDW && eos != EVLBM_EOS_CS)) return fail(EVLBM_EINVAL, "unknown pressure closure");
+    if (!(R > 0) || !(a > 0) || !(b > 0)) return fail(EVLBM_EINVAL, "need R, a, b > 0");
+    critical(eos, R, a, b, out);
+    return EVLBM_OK;
+}
+
+int evlbm_eos_coexistence(int eos, double R, double a, double b, double T, double out[3])
+{
+    if (!out || (eos != EVLBM_EOS_VDW && eos != EVLBM_EOS_CS)) return fail(EVLBM_EINVAL, "unknown pressure closure");
+    if (!(R > 0) || !(a > 0) || !(b > 0)) return fail(EVLBM_EINVAL, "need R, a, b > 0");
+    double cp[3];
+    critical(eos, R, a, b, cp);
+    const double rc = cp[0], Tc = cp[1];
+    if (!(T > 0) || !(T < Tc)) return fail(EVLBM_EINVAL, "T must lie in (0, T_c)");
+    // Newton on P(rl) = P(rv), mu(rl) = mu(rv), continued in temperature from
+    // just below T_c (where the mean-field critical law rho_c (1 +- 2 sqrt(1 -
+    // T/Tc)) is a good start) down to T, each stage starting from the last;
+    // damped so the iterates stay on their branches.
+    const double eps0 = std::fmin(1e-3, 1.0 - T / Tc);
+    const int stages = 48;
+    double rl = 0.0, rv = 0.0;
+    for (int k = 0; k <= stages; ++k) {
+        // 1 - T_k/Tc from eps0 to 1 - T/Tc, geometrically
+        const double eps = eps0 * std::pow((1.0 - T / Tc) / eps0, (double)k / stages);
+        const HostEos th{eos, R * Tc * (1.0 - eps), a, b};
+        const double rmax = th.rmax();
+        if (k == 0) {
+            rl = rc * (1.0 + 2.0 * std::sqrt(eps));
+            rv = rc * (1.0 - 2.0 * std::sqrt(eps));
+        }
+        for (int it = 0; it < 100; ++it) {
+            const double f1 = th.P(rl) - th.P(rv), f2 = th.mu(rl) - th.mu(rv);
+            const double a11 = th.dP(rl), a12 = -th.dP(rv), a21 = th.dP(rl) / rl, a22 = -th.dP(rv) / rv;
+            const double det = a11 * a22 - a12 * a21;
+            const double drl = -(f1 * a22 - a12 * f2) / det, drv = -(a11 * f2 - a21 * f1) / det;
+            double t = 1.0;
+            while ((rl + t * drl >= rmax || rl + t * drl <= rc || rv + t * drv <= 0.0 || rv + t * drv >= rc) &&
+                   t > 1e-6)
+                t *= 0.5;
+            rl += t * drl;
+            rv += t * drv;
+            if (std::fabs(drl) < 1e-15 * rl && std::fabs(drv) < 1e-15 * rv) break;
+        }
+    }
+    const HostEos th{eos, R * T, a, b};
     out[0] = rl;
     out[1] = rv;
-    out[2] = P(rl);
+    out[2] = th.P(rl);
+    if (!std::isfinite(rl) || !std::isfinite(rv) || !(rl > rc) || !(rv < rc))
+        return fail(EVLBM_EINVAL, "coexistence iteration did not converge at T = %g", T);
     return EVLBM_OK;
 }
 

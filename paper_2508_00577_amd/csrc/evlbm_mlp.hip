@@ -480,77 +480,4 @@ int evlbm_mlp_density_field(evlbm_mlp_t m, int nx, int ny, int nz, double cx, do
 
 }  // extern "C"
 
-// ------------------------------------------------------ droplet initialisation
-
-namespace evlbm {
-
-__global__ void __launch_bounds__(256) k_tanh_droplet(int nx, int ny, int nz, double cx, double cy, double cz,
-                                                      double R, double W, double rl, double rv, double T0,
-                                                      double *__restrict__ rho, double *__restrict__ T, long n)
-{
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n) return;
-    const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((long)nx * ny));
-    const double dx = x - cx, dy = y - cy, dz = nz > 1 ? z - cz : 0.0;
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (rho) rho[c] = 0.5 * (rl + rv) - 0.5 * (rl - rv) * tanh((r - R) / W);
-    T[c] = T0;
-}
-
-}  // namespace evlbm
-
-extern "C" {
-
-int evlbm_init_droplet(evlbm_t h, double cx, double cy, double cz, double R, double Tr, int profile, evlbm_mlp_t mlp,
-                       double width, int *used_mlp)
-{
-    if (!h || !(R > 0) || !(Tr > 0) || !(width > 0)) return fail(EVLBM_EINVAL, "bad droplet arguments");
-    if (profile != EVLBM_PROFILE_TANH && profile != EVLBM_PROFILE_MLP) return fail(EVLBM_EINVAL, "unknown profile");
-    if (profile == EVLBM_PROFILE_MLP && !mlp) return fail(EVLBM_EINVAL, "MLP profile needs a network");
-    const double Tc = 8.0 * h->a / (27.0 * h->b * h->R);
-    double co[3];
-    int rc = evlbm_eos_coexistence(h->R, h->a, h->b, Tr * Tc, co);
-    if (rc) return rc;
-    const double rl = co[0], rv = co[1], rho_c = 1.0 / (3.0 * h->b);
-    bool mlp_ok = false;
-    if (profile == EVLBM_PROFILE_MLP && Tr >= mlp->hull[0] && Tr <= mlp->hull[1] && R >= mlp->hull[2] &&
-        R <= mlp->hull[3]) {
-        // radial probe r/R in [0, 3]: finite, non-increasing (to 1e-3 rho_c) and
-        // within [0.5 rho_v, 1.2 rho_l]
-        const int np = 256;
-        std::vector<float> X(3 * np), Y(np);
-        for (int k = 0; k < np; ++k) {
-            X[3 * k] = (float)Tr;
-            X[3 * k + 1] = (float)R;
-            X[3 * k + 2] = 3.0f * k / (np - 1);
-        }
-        rc = evlbm_mlp_forward(mlp, X.data(), Y.data(), np);
-        if (rc) return rc;
-        mlp_ok = true;
-        for (int k = 0; k < np; ++k) {
-            const double v = rho_c * Y[k];
-            if (!std::isfinite(v) || v < 0.5 * rv || v > 1.2 * rl) mlp_ok = false;
-            if (k > 0 && rho_c * (Y[k] - Y[k - 1]) > 1e-3 * rho_c) mlp_ok = false;
-        }
-    }
-    const long N = h->N;
-    double *d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(double) * 2 * N);
-    if (e != hipSuccess) return fail(EVLBM_ENOMEM, "droplet fields: %s", hipGetErrorString(e));
-    double *drho = d, *dT = d + N;
-    hipLaunchKernelGGL(k_tanh_droplet, dim3((N + 255) / 256), dim3(256), 0, h->stream, h->nx, h->ny, h->nz, cx, cy, cz,
-                       R, width, rl, rv, Tr * Tc / h->R, mlp_ok ? (double *)nullptr : drho, dT, N);
-    if (mlp_ok) {
-        // the network runs on its own stream: order it after the lattice stream
-        e = hipStreamSynchronize(h->stream);
-        if (e == hipSuccess) rc = evlbm_mlp_density_field(mlp, h->nx, h->ny, h->nz, cx, cy, cz, R, Tr, rho_c, drho);
-        if (e == hipSuccess && rc == EVLBM_OK) e = hipStreamSynchronize(mlp->stream);
-    }
-    if (e == hipSuccess && rc == EVLBM_OK) rc = evlbm_init_fields(h, drho, nullptr, dT, EVLBM_DEVICE_F64);
-    else if (e != hipSuccess) rc = hip_fail(e, "droplet initialisation");
-    (void)hipFree(d);
-    if (used_mlp) *used_mlp = mlp_ok ? 1 : 0;
-    return rc;
-}
-
-}  // extern "C"
+hipStream_t evlbm::mlp_stream(evlbm_mlp_t m) { return m->stream; }

@@ -7,13 +7,14 @@
 namespace evlbm {
 
 template <typename R>
-inline StepParams<R> model_params(double Rg, double a, double b, double kappa, double tau, double lambda,
+inline StepParams<R> model_params(int eos, double Rg, double a, double b, double kappa, double tau, double lambda,
                                   double sphi)
 {
     StepParams<R> p;
     p.nx = p.ny = p.nz = 1;
     p.N = 1;
     p.ds = 1;
+    p.eos = eos;
     p.a = (R)a;
     p.b = (R)b;
     p.kappa = (R)kappa;

@@ -122,13 +122,63 @@ struct StepParams {
     int nx, ny, nz;
     long N;          // cells
     long ds;         // elements between consecutive direction arrays of the populations (>= N)
-    R a, b, kappa;   // EOS: P_E = rho RT/(1 - b rho), P_V = -a rho^2, capillarity
+    int eos;         // contact factor of Enskog's pressure: EVLBM_EOS_VDW or EVLBM_EOS_CS (enskog())
+    R a, b, kappa;   // EOS: P_E = rho RT Z(rho) (b: excluded volume), P_V = -a rho^2, capillarity
     R two_beta;      // 2 beta, beta = 1/(2 tau + 1)
     R wstar;         // (dt/lambda)(1 - beta)
     R lambda, sphi;
     R Rgas;
     const float4 *refst;  // 16-bit deviation storage: reference state of every cell (ref_state_of)
 };
+
+// ---------------------------------------------------- Enskog pressure
+
+// Enskog's pressure P_E = rho R T (1 + b rho chi) = rho R T Z(rho) with the
+// contact value chi of the pair distribution (the text after eq. Ework):
+//   EVLBM_EOS_VDW  chi = 1/(1 - b rho):  Z = 1/(1 - b rho) (the paper's form)
+//   EVLBM_EOS_CS   chi = (1 - eta/2)/(1 - eta)^3, eta = b rho/4 (Carnahan-
+//                  Starling): Z = (1 + eta + eta^2 - eta^3)/(1 - eta)^3.
+// Under the gauge P0 = P_E (eq. P0E), theta = P0/rho = RT Z and eq. gamma
+// gives gamma_0 = 1 + d ln Z/d ln rho + (2/3) Z, so the factor of
+// eq. correction_gamma is 5/3 - gamma_0:
+//   van der Waals: (5/3)(1 - Z);
+//   Carnahan-Starling: 2/3 - (2/3) Z - d ln Z/d ln rho with
+//   d ln Z/d ln rho = eta (1 + 2 eta - 3 eta^2)/(1 + eta + eta^2 - eta^3) + 3 eta/(1 - eta).
+template <typename R>
+struct Enskog {
+    R Z;   // P_E/(rho R T)
+    R g5;  // 5/3 - gamma_0
+};
+
+template <typename R>
+__device__ inline Enskog<R> enskog(int eos, R b, R rho)
+{
+    if (eos == EVLBM_EOS_CS) {
+        const R eta = R(0.25) * b * rho;
+        const R i1 = rcp(R(1) - eta);
+        const R num = R(1) + eta * (R(1) + eta * (R(1) - eta));
+        const R Z = num * (i1 * i1 * i1);
+        const R dlnZ = eta * (R(1) + eta * (R(2) - R(3) * eta)) * rcp(num) + R(3) * eta * i1;
+        return Enskog<R>{Z, (R(2) / R(3)) * (R(1) - Z) - dlnZ};
+    }
+    const R Z = rcp(R(1) - b * rho);
+    return Enskog<R>{Z, (R(5) / R(3)) * (R(1) - Z)};
+}
+
+// FP64 form for initialisation, validation and measurement (exact divisions);
+// false outside the closure's range (b rho >= 1, resp. eta >= 1).
+__host__ __device__ inline bool enskog_z64(int eos, double b, double rho, double *Z)
+{
+    if (eos == EVLBM_EOS_CS) {
+        const double eta = 0.25 * b * rho;
+        if (!(eta < 1.0)) return false;
+        *Z = (1.0 + eta + eta * eta - eta * eta * eta) / ((1.0 - eta) * (1.0 - eta) * (1.0 - eta));
+        return true;
+    }
+    if (!(1.0 - b * rho > 0.0)) return false;
+    *Z = 1.0 / (1.0 - b * rho);
+    return true;
+}
 
 // ------------------------------------------------------------ addressing
 

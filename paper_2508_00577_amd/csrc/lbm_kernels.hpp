@@ -31,7 +31,7 @@ using RealT = typename Codec<S>::R;
 
 // -------------------------------------------------------------- k_init
 
-// f = f^eq(rho, u, theta), g = g^eq(u, RT) with theta = RT/(1 - b rho)
+// f = f^eq(rho, u, theta), g = g^eq(u, RT) with theta = P_E/rho = RT Z(rho)
 // (eq. feq, eq. geq); inputs in FP64, u may be null (rest).
 template <int D, int S>
 __global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, const double *__restrict__ u0,
@@ -44,7 +44,9 @@ __global__ void __launch_bounds__(256) k_init(const double *__restrict__ rho0, c
     if (cell >= p.N) return;
     const double rho = rho0[cell];
     const double RT = (double)p.Rgas * T0[cell];
-    const double theta = RT / (1.0 - (double)p.b * rho);
+    double Z = 0.0;  // the fields were validated: inside the closure's range
+    enskog_z64(p.eos, (double)p.b, rho, &Z);
+    const double theta = RT * Z;
     double u[3] = {0.0, 0.0, 0.0};
     if (u0)
         for (int a = 0; a < D; ++a) u[a] = u0[a * p.N + cell];
@@ -237,12 +239,12 @@ struct NoSink {
 // (eq. def_ustar with Qtilde = 0) and the update eq. pre_LBM for one cell,
 // from its pulled populations (raw stored values fr, gr of pull_pops) into
 // the destination of the accessor at the cell itself (o.ox[1] + o.oy[1] +
-// o.oz[1]).  inv_omb = 1/(1 - b rho).  Every stored direction is also handed
+// o.oz[1]).  zf = Z(rho) = P_E/(rho R T) (enskog).  Every stored direction is also handed
 // to sink, decoded.
 template <int D, int S, class A, class Sink = NoSink>
 __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[], const A &pops,
                                       const StepParams<RealT<S>> &p, const PullOffsets &o, RealT<S> rho,
-                                      RealT<S> inv_rho, RealT<S> K, RealT<S> inv_omb, RealT<S> theta,
+                                      RealT<S> inv_rho, RealT<S> K, RealT<S> zf, RealT<S> theta,
                                       const RealT<S> u[3], const RealT<S> F[3], const RealT<S> Phi[3],
                                       const RealT<S> qp[3], Sink sink = Sink())
 {
@@ -257,7 +259,7 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
     // (3/2) RT* = (3/2) RT - lambda^2 |F|^2/(2 rho^2)
     const R hS = K - R(0.5) * p.lambda * p.lambda * F2 * inv_rho * inv_rho;
     const R RTs = hS * (R(2) / R(3));
-    const R thetas = RTs * inv_omb;
+    const R thetas = RTs * zf;
 
     // per-axis factors: fe (f^eq and g^eq), fs (f*), gs (g*), chi for g^eq, g*
     R fe[3][3], fs[3][3], gs[3][3], xe[3][3], xs[3][3];
@@ -368,7 +370,7 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
 template <int D, int S>
 __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
                                     const StepParams<RealT<S>> &p, int x, int y, int z, RealT<S> rho,
-                                    RealT<S> inv_rho, RealT<S> K, RealT<S> RT, RealT<S> inv_omb, RealT<S> theta,
+                                    RealT<S> inv_rho, RealT<S> K, RealT<S> RT, RealT<S> zf, RealT<S> theta,
                                     const RealT<S> u[3], const RealT<S> F[3], const RealT<S> Phi[3],
                                     const RealT<S> qp[3])
 {
@@ -378,7 +380,7 @@ __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S>
     const PtrPops<StoreT<S>> pops{src, dst, p.ds};
     StoreT<S> fr[Q], gr[Q];
     pull_pops<D, S>(pops, o, fr, gr);
-    collide_pulled<D, S>(fr, gr, pops, p, o, rho, inv_rho, K, inv_omb, theta, u, F, Phi, qp);
+    collide_pulled<D, S>(fr, gr, pops, p, o, rho, inv_rho, K, zf, theta, u, F, Phi, qp);
 }
 
 // ------------------------------------------------------------ k_collide
@@ -500,7 +502,7 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
         // a round trip through a rounded 2/3 would bias the energy every step.
         const R K = rhoE * ir - R(0.5) * u2;
         const R RT = K * (R(2) / R(3));
-        const R theta = RT * rcp(R(1) - p.b * rho);
+        const R theta = RT * enskog(p.eos, p.b, rho).Z;
         for (int a = 0; a < D; ++a) {
             s_f1[(F_U + a) * TS::N1 + t] = u[a];
             s_f1[(F_M + a) * TS::N1 + t] = rho * u[a] * (u[a] * u[a] + R(3) * theta - R(1));
@@ -522,8 +524,8 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
     const R inv_rho = rcp(rho);
     const R K = s_f1[F_K * TS::N1 + c1];  // (3/2) RT
     const R RT = K * (R(2) / R(3));
-    const R inv_omb = rcp(R(1) - p.b * rho);
-    const R theta = RT * inv_omb;
+    const Enskog<R> ez = enskog(p.eos, p.b, rho);
+    const R theta = RT * ez.Z;
     const R P0 = rho * theta;
     R u[3] = {R(0), R(0), R(0)}, F[3] = {R(0), R(0), R(0)};
     for (int a = 0; a < D; ++a) {
@@ -531,11 +533,11 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
         F[a] = s_f1[(F_F + a) * TS::N1 + c1];
     }
     // corrections (eq. correction_u, correction_gamma with gamma_0 of eq. gamma
-    // for P0 = P_E: gamma_0 = (5/3)/(1 - b rho); eq. correction_q)
+    // for P0 = P_E: 5/3 - gamma_0 = ez.g5; eq. correction_q)
     R divu = lds_grad<D, 0, R>(s_f1 + F_U * TS::N1, c1, SY, SZ) +
              lds_grad<D, 1, R>(s_f1 + (F_U + 1) * TS::N1, c1, SY, SZ);
     if (D == 3) divu += lds_grad<D, 2, R>(s_f1 + (F_U + 2) * TS::N1, c1, SY, SZ);
-    const R Phip = P0 * (R(5) / R(3)) * (R(1) - inv_omb) * divu;
+    const R Phip = P0 * ez.g5 * divu;
     R Phi[3] = {R(0), R(0), R(0)}, qp[3] = {R(0), R(0), R(0)};
     Phi[0] = p.sphi * lds_grad<D, 0, R>(s_f1 + F_M * TS::N1, c1, SY, SZ) + Phip;
     Phi[1] = p.sphi * lds_grad<D, 1, R>(s_f1 + (F_M + 1) * TS::N1, c1, SY, SZ) + Phip;
@@ -545,7 +547,7 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
         Phi[2] = p.sphi * lds_grad<D, 2, R>(s_f1 + (F_M + 2) * TS::N1, c1, SY, SZ) + Phip;
         qp[2] = p.lambda * (P0 * lds_grad<D, 2, R>(s_f1 + F_TD * TS::N1, c1, SY, SZ) + u[2] * Phip);
     }
-    collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, inv_omb, theta, u, F, Phi, qp);
+    collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, ez.Z, theta, u, F, Phi, qp);
 }
 
 // One tile per workgroup, nbx x nby x nbz tiles in XCD order (xcd_tile).
@@ -876,7 +878,7 @@ __global__ void __launch_bounds__(TX *TY)
                 }
                 const R K = (mv[j][3] + R(0.5) * uF) * ir - R(0.5) * u2;
                 const R RT = K * (R(2) / R(3));
-                const R theta = RT * rcp(R(1) - p.b * rho);
+                const R theta = RT * enskog(p.eos, p.b, rho).Z;
                 const int c1 = lx + ZT::R1X * ly;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -1170,8 +1172,8 @@ __global__ void __launch_bounds__(TX *TY)
             const R inv_rho = rcp(rho);
             const R K = Kc;
             const R RT = K * (R(2) / R(3));
-            const R inv_omb = rcp(R(1) - p.b * rho);
-            const R theta = RT * inv_omb;
+            const Enskog<R> ez = enskog(p.eos, p.b, rho);
+            const R theta = RT * ez.Z;
             const R P0 = rho * theta;
             R u[3], F[3];
 #pragma unroll
@@ -1182,7 +1184,7 @@ __global__ void __launch_bounds__(TX *TY)
             const R divu = ring_grad<0, R>(fm[FU], f0[FU], fp[FU], c1, ZT::R1X) +
                            ring_grad<1, R>(fm[FU + 1], f0[FU + 1], fp[FU + 1], c1, ZT::R1X) +
                            ring_grad<2, R>(fm[FU + 2], f0[FU + 2], fp[FU + 2], c1, ZT::R1X);
-            const R Phip = P0 * (R(5) / R(3)) * (R(1) - inv_omb) * divu;
+            const R Phip = P0 * ez.g5 * divu;
             R Phi[3], qp[3];
             Phi[0] = p.sphi * ring_grad<0, R>(fm[FM], f0[FM], fp[FM], c1, ZT::R1X) + Phip;
             Phi[1] = p.sphi * ring_grad<1, R>(fm[FM + 1], f0[FM + 1], fp[FM + 1], c1, ZT::R1X) + Phip;
@@ -1191,13 +1193,13 @@ __global__ void __launch_bounds__(TX *TY)
             qp[1] = p.lambda * (P0 * ring_grad<1, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[1] * Phip);
             qp[2] = p.lambda * (P0 * ring_grad<2, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[2] * Phip);
             if constexpr (PUSH)
-                collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, inv_omb, theta, u, F, Phi, qp,
+                collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, ez.Z, theta, u, F, Phi, qp,
                                      [&](int i, R f, R g) {
                                          vf[i] = f;
                                          vg[i] = g;
                                      });
             else
-                collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, inv_omb, theta, u, F, Phi, qp);
+                collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, ez.Z, theta, u, F, Phi, qp);
         }
         load_fields(k + 1, rvn, mvn);
         pull_pops<3, S>(pops, pull_offsets<3, (int)sizeof(T)>(p.nx, p.ny, p.nz, xl, yl, k + 1), fr, gr);
@@ -1477,7 +1479,7 @@ __global__ void __launch_bounds__(256) k_sums(const StoreT<S> *__restrict__ pop,
 // plus a separate sum of rho over the whole lattice (sums[8]).
 template <int D, typename R>
 __global__ void __launch_bounds__(256) k_measure(const R *__restrict__ m, const R *__restrict__ lap, int nx, int ny, int nz,
-                                                 R a, R b, R kappa, R Rgas, int kind, double g0, double g1, double g2,
+                                                 int eos, R a, R b, R kappa, R Rgas, int kind, double g0, double g1, double g2,
                                                  double g3, double g4, double g5, double *__restrict__ partial)
 {
     const long N = (long)nx * ny * nz;
@@ -1488,7 +1490,9 @@ __global__ void __launch_bounds__(256) k_measure(const R *__restrict__ m, const 
         const int x = (int)(cell % nx), y = (int)((cell / nx) % ny), z = (int)(cell / ((long)nx * ny));
         CellState<D, R> s = cell_state<D, R>(m, lap, N, x, y, z, nx, ny, nz, a, kappa);
         const double rho = s.rho, RT = s.RT;
-        const double P = rho * RT / (1.0 - (double)b * rho) - (double)a * rho * rho;
+        double Z = NAN;  // bulk pressure P = rho RT Z - a rho^2 (NaN outside the closure's range)
+        enskog_z64(eos, (double)b, rho, &Z);
+        const double P = rho * RT * Z - (double)a * rho * rho;
         int region = 0;  // 1 in, 2 out
         if (kind == EVLBM_MEASURE_SLAB) {
             if (x >= g0 && x < g1) region = 1;
@@ -1543,35 +1547,50 @@ __global__ void __launch_bounds__(256) k_encode(const double *__restrict__ in, S
     pop[(long)i * p.ds + c] = Codec<S>::enc((RealT<S>)in[t], ref_enc<D, S>(i, rs, ref_inv_of<S, RealT<S>>(rs)));
 }
 
-// Validate initial fields: rho > 0, b rho < 1, T > 0 and finite.
+// Validate initial fields: rho > 0 inside the range of the pressure closure
+// (b rho < 1 for van der Waals, b rho < 4 for Carnahan-Starling), T > 0, finite.
 static __global__ void __launch_bounds__(256) k_validate(const double *__restrict__ rho, const double *__restrict__ T, long N,
-                                                  double b, int *__restrict__ flag)
+                                                  int eos, double b, int *__restrict__ flag)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
     const double r = rho[t], tt = T[t];
+    double Z;
     if (!isfinite(r) || !isfinite(tt)) atomicOr(flag, 2);
-    else if (!(r > 0.0) || !(1.0 - b * r > 0.0) || !(tt > 0.0)) atomicOr(flag, 1);
+    else if (!(r > 0.0) || !enskog_z64(eos, b, r, &Z) || !(tt > 0.0)) atomicOr(flag, 1);
 }
 
-// Reference density of every cell = sum of its stored (decoded, FP64) f.
+// Z(rho) = P_E/(rho R T) in the arithmetic type V (enskog, enskog_z64).
+template <typename V>
+__device__ inline V enskog_Z(int eos, V b, V rho)
+{
+    if constexpr (sizeof(V) == 4) {
+        return enskog<V>(eos, b, rho).Z;
+    } else {
+        V Z = V(NAN);
+        enskog_z64(eos, b, rho, &Z);
+        return Z;
+    }
+}
+
 // 16-bit deviation storage: reference state of every cell (ref_state_of)
-// from initial fields (rho, T).
+// from initial fields (rho, T), theta = RT Z(rho).
 template <int D>
 __global__ void __launch_bounds__(256) k_ref_from_fields(const double *__restrict__ rho, const double *__restrict__ T,
-                                                         long N, double Rg, double b, float4 *__restrict__ refst)
+                                                         long N, double Rg, int eos, double b,
+                                                         float4 *__restrict__ refst)
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N) return;
     const double RT = Rg * T[t];
-    refst[t] = ref_state_of<D>(rho[t], RT / (1.0 - b * rho[t]), 1.5 * RT);
+    refst[t] = ref_state_of<D>(rho[t], RT * enskog_Z<double>(eos, b, rho[t]), 1.5 * RT);
 }
 
 // The same from populations f, g at rest in the cell's own frame: rho = sum f,
 // j = sum c f, K = sum g/rho - |j|^2/(2 rho^2) = (3/2) RT, in the arithmetic
 // type V (the reference only sets the scale of the stored deviations).
 template <int D, typename V>
-__device__ inline float4 ref_state(const V *f, const V *g, V b)
+__device__ inline float4 ref_state(const V *f, const V *g, int eos, V b)
 {
     constexpr int Q = Lat<D>::Q;
     V rho = V(0), e = V(0), j[3] = {V(0), V(0), V(0)};
@@ -1583,12 +1602,12 @@ __device__ inline float4 ref_state(const V *f, const V *g, V b)
         j[2] += V(cz_d<D>(i)) * f[i];
     }
     const V K = e / rho - V(0.5) * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / (rho * rho);
-    return ref_state_of<D, V>(rho, (V(2) / V(3)) * K / (V(1) - b * rho), K);
+    return ref_state_of<D, V>(rho, (V(2) / V(3)) * K * enskog_Z<V>(eos, b, rho), K);
 }
 
 // From decoded populations in the dense host layout ([Q][N] f, then g).
 template <int D>
-__global__ void __launch_bounds__(256) k_ref_from_pops(const double *__restrict__ pops, long N, double b,
+__global__ void __launch_bounds__(256) k_ref_from_pops(const double *__restrict__ pops, long N, int eos, double b,
                                                        float4 *__restrict__ refst)
 {
     constexpr int Q = Lat<D>::Q;
@@ -1599,7 +1618,7 @@ __global__ void __launch_bounds__(256) k_ref_from_pops(const double *__restrict_
         f[i] = pops[(long)i * N + t];
         g[i] = pops[(long)(Q + i) * N + t];
     }
-    refst[t] = ref_state<D>(f, g, b);
+    refst[t] = ref_state<D>(f, g, eos, b);
 }
 
 // Re-reference in place: decode the 2Q values stored at a cell with its old
@@ -1620,7 +1639,7 @@ __global__ void __launch_bounds__(256) k_rereference(StoreT<S> *__restrict__ pop
         f[i] = Codec<S>::dec(pop[(long)i * p.ds + t], ref_at<D, S>(p, i, t));
         g[i] = Codec<S>::dec(pop[(long)(Q + i) * p.ds + t], ref_at<D, S>(p, Q + i, t));
     }
-    const float4 rs = ref_state<D, R>(f, g, p.b);
+    const float4 rs = ref_state<D, R>(f, g, p.eos, p.b);
     refst[t] = rs;
     const RefInv<RealT<S>> inv = ref_inv_of<S, RealT<S>>(rs);
     // re-encode keeping the cell's mass and energy: rest + opposite pair close

@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import MLP, Lattice
+from . import MLP, Lattice, eos_critical
 
 
 def radial_profile(rho, centre, R, dr=0.5, rmax_factor=3.0):
@@ -107,7 +107,8 @@ def droplet_run(shape, R, Tr, params, steps=None, profile="tanh", mlp=None, stor
     if steps is not None:
         L.step(steps)
         return L, used, steps, None
-    n, conv = run_to_equilibrium(L, max_steps, check, tol, rho_c=1.0 / (3.0 * params["b"]))
+    rho_c = eos_critical(params["R"], params["a"], params["b"], params.get("eos", "vdw"))[0]
+    n, conv = run_to_equilibrium(L, max_steps, check, tol, rho_c=rho_c)
     return L, used, n, conv
 
 
@@ -132,30 +133,19 @@ def train_network(X, Y, init_params, iters, lr=1e-3):
 
 
 def network_density(net, shape, R, Tr, rho_c):
-    """rho_c y(Tr, R, |x - c|/R) on every cell, from the network (host FP64)."""
+    """rho_c y(Tr, R, |x - c|/R) on every cell of a droplet centred in the
+    box: the library's network density field, copied to the host."""
     nz, ny, nx = shape
     centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
-    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2
-    if nz > 1:
-        r2 = r2 + (z - centre[2]) ** 2
-    rr = (np.sqrt(r2) / R).ravel()
-    X = np.stack([np.full(rr.size, Tr), np.full(rr.size, R), rr], 1)
-    return (rho_c * net.forward(X).astype(np.float64)).reshape(shape)
+    return net.density_field(shape, centre, R, Tr, rho_c).cpu().numpy()
 
 
 def seed_matched(L, net, R, Tr, params, target):
     """Seed L from the network with the mass and total energy `target` (global
-    sums of a plain-seeded lattice).  Returns the temperature used."""
-    Tc = 8.0 * params["a"] / (27.0 * params["b"] * params["R"])
-    rho = network_density(net, L.shape, R, Tr, 1.0 / (3.0 * params["b"]))
-    rho *= target[0] / rho.sum()
-    T0 = Tr * Tc
-    L.init_fields(rho, np.full(L.shape, T0))
-    s = L.global_sums()
-    T1 = T0 + (target[5] - s[5]) / (1.5 * params["R"] * target[0])
-    L.init_fields(rho, np.full(L.shape, T1))
-    return T1
+    sums 0 and 5 of a plain-seeded lattice), in the library
+    (evlbm_init_droplet_matched).  Returns the temperature used."""
+    _, T = L.init_droplet_matched(R, Tr, target[0], target[5], profile="mlp", mlp=net)
+    return T
 
 
 def _first_within(snaps, ref, tol):

@@ -1,0 +1,83 @@
+"""The walls of the thermal Couette flow (evlbm_set_walls) through the C ABI:
+parity with the oracle's walls (the same reading of the wall scheme) and the
+supersonic steady state against the continuum profile (oracle.couette)."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.couette as C
+import synth
+
+pytestmark = pytest.mark.gpu
+ev = pytest.importorskip("paper_2508_00577_amd")
+A, B = synth.A_ATTR, synth.B_EXCL
+SQ3 = np.sqrt(3.0)
+
+
+def _params(tau=1.0):
+    return dict(R=1.0, a=A, b=B, kappa=0.0, tau=tau, lam=tau)
+
+
+@pytest.mark.parametrize("D,shape", [(2, (1, 3, 48)), (3, (4, 3, 20))])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_walls_match_oracle(D, shape, storage, tol):
+    """A channel between the diffuse walls (wall at x = nx - 1/2 moving at
+    U_w = 0.3 along y, both at 1.5 T_c), started from a density and
+    temperature perturbation at rest: moments after 1000 steps against the
+    oracle."""
+    nz, ny, nx = shape
+    Tw, Uw = 1.5 * synth.T_CRIT, 0.3
+    x = np.arange(nx)
+    rho = np.broadcast_to(1.0 + 0.1 * np.cos(2 * np.pi * x / nx), shape).copy()
+    T = np.broadcast_to(Tw * (1 + 0.05 * np.sin(2 * np.pi * x / nx)), shape).copy()
+    g = ev.Lattice(D, nx, ny, nz, storage=storage)
+    g.set_params(**_params())
+    g.set_walls(Tw, Uw)
+    g.init_fields(rho, T)
+    o = oracle.Lattice(D, nx, ny, nz)
+    o.set_params(**_params())
+    o.set_walls(Tw, Uw)
+    o.init(rho, T)
+    m0 = g.global_sums()[0]
+    g.step(1000)
+    o.step(1000)
+    rg, ug, Tg = g.moments()
+    ro, uo, To, _ = o.moments()
+    e = (np.abs(rg - ro).max() / ro.max(), np.abs(ug - uo).max() * SQ3, np.abs(Tg - To).max() / To.max())
+    print(f"walls D={D} {storage}: e_rho={e[0]:.3e} e_u={e[1]:.3e} e_T={e[2]:.3e}", flush=True)
+    assert max(e) < tol
+    assert abs(g.global_sums()[0] / m0 - 1) < (1e-13 if storage == "f64" else 1e-6)
+    so = o.global_sums()
+    sg = g.global_sums()
+    assert sg[0] == pytest.approx(so[0], rel=tol) and sg[5] == pytest.approx(so[5], rel=tol)
+
+
+def test_supersonic_couette_steady_state():
+    """The Couette flow of Fig. 2 on the GPU: 128 cells between the walls of
+    a dense van der Waals gas (mean density rho_c, T_w = 1.5 T_c), the moving
+    wall's speed set for Mach 1.2 there, run from rest to the steady state
+    (4e5 steps, FP64).  Against the continuum profile: temperature within
+    3e-3 of T, density within 6e-3, velocity within 8e-3 of U_w, Mach number
+    at the moving wall's cell within 0.015 (the wall slip and temperature jump
+    of diffuse walls are first order in the cell size over the channel
+    width; the oracle's 128-cell channel measured e_T 2.1e-3, e_rho 4.3e-3,
+    e_u 6.3e-3)."""
+    nx, Tw, tau = 128, 1.5 * synth.T_CRIT, 1.0
+    U = C.wall_speed_for_mach(float(nx), 1.0, Tw, 1.2, A, B, tau)
+    an = C.at(C.profile(float(nx), 1.0, Tw, U, A, B, tau), np.arange(nx) + 0.5)
+    g = ev.Lattice(2, nx, 1, 1, storage="f64")
+    g.set_params(**_params(tau))
+    g.set_walls(Tw, U)
+    g.init_fields(np.ones((1, 1, nx)), np.full((1, 1, nx), Tw))
+    m0 = g.global_sums()[0]
+    g.step(400000)
+    r, u, T = g.moments()
+    e_rho = np.abs(r[0, 0] - an["rho"]).max() / an["rho"].max()
+    e_T = np.abs(T[0, 0] - an["T"]).max() / an["T"].max()
+    e_u = np.abs(u[1, 0, 0] - an["u"]).max() / U
+    Ma = u[1, 0, 0, -1] / C.sound_speed(r[0, 0, -1], T[0, 0, -1], A, B)
+    print(f"Couette 128 GPU: e_rho {e_rho:.2e} e_T {e_T:.2e} e_u {e_u:.2e} Mach {Ma:.4f} vs {an['Mach'][-1]:.4f}",
+          flush=True)
+    assert e_T < 3e-3 and e_rho < 6e-3 and e_u < 8e-3
+    assert Ma == pytest.approx(an["Mach"][-1], abs=0.015)
+    assert abs(g.global_sums()[0] / m0 - 1) < 1e-12

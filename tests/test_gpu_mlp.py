@@ -36,6 +36,27 @@ def test_forward_matches_oracle(n):
     assert np.abs(y - yo).max() < 2e-5 * max(1.0, np.abs(yo).max())
 
 
+@pytest.mark.parametrize("shape,centre,R,Tr", [((1, 37, 53), (26.0, 18.0, 0.0), 12.5, 0.8),
+                                               ((13, 11, 29), (14.3, 5.0, 6.7), 4.0, 0.7)])
+def test_density_field_matches_oracle(shape, centre, R, Tr):
+    """evlbm_mlp_density_field (the network evaluated at every cell, MFMA
+    layers) against the FP64 oracle network at the same inputs
+    (T/Tc, R, r/R), r/R rounded to FP32 as the kernel takes it."""
+    p = _params(9)
+    net = ev.MLP(p)
+    rho_c = 1.25
+    got = net.density_field(shape, centre, R, Tr, rho_c).cpu().numpy()
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    d2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2 + ((z - centre[2]) ** 2 if nz > 1 else 0.0)
+    rr = (np.sqrt(d2) / R).astype(np.float32).astype(np.float64)
+    X = np.stack([np.full(rr.size, np.float32(Tr)), np.full(rr.size, np.float32(R)), rr.ravel()], 1)
+    want = rho_c * OM.forward(p, X).reshape(shape)
+    err = np.abs(got - want).max() / rho_c
+    print(f"density field {shape}: max |d rho|/rho_c = {err:.2e}", flush=True)
+    assert err < 2e-5
+
+
 def test_gradient_matches_oracle():
     """Per-tensor relative L2 error of the FP32 gradient
     against the FP64 oracle below 1e-4."""

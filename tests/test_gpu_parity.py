@@ -258,13 +258,20 @@ def test_3d_z_chunks_and_thin_lattices(shape, steps):
     _compare(g, o, 1e-11, f"3d {shape} f64 step {steps}")
 
 
+BF16_3D = ("BF16 deviation storage misses the 1e-3 density bar in 3D (8-bit significand; measured "
+           "1.05e-3 against FP32 after 300 steps here, 1.26e-3 at 128^3 after 1e4 steps, 2.99e-3 against the "
+           "oracle on 37 x 11 x 13 after 1000 steps); the library keeps it as an experimental storage")
+
+
 @pytest.mark.parametrize("D,shape,storage", [(2, (1, 40, 96), "f16dev"), (2, (1, 40, 96), "bf16dev"),
-                                             (3, (24, 20, 36), "f16dev"), (3, (24, 20, 36), "bf16dev")])
+                                             (3, (24, 20, 36), "f16dev"),
+                                             pytest.param(3, (24, 20, 36), "bf16dev",
+                                                          marks=pytest.mark.skip(reason=BF16_3D))])
 def test_16bit_deviation_storage_tracks_fp32(D, shape, storage):
     """Populations stored as 16-bit deviations from the equilibrium at rest of
     a per-cell reference state (re-referenced every 100 steps), FP32
-    arithmetic, against the FP32-storage run after 300 steps.  FP16 (11-bit
-    significand) meets the 1e-3 density target; BF16 (8-bit) is held to 3e-2."""
+    arithmetic, against the FP32-storage run after 300 steps: density within
+    the 1e-3 target."""
     rho, T = _state("droplet", shape, 0.8, 1e-4)
     nz, ny, nx = shape
     runs = {}
@@ -276,7 +283,7 @@ def test_16bit_deviation_storage_tracks_fp32(D, shape, storage):
         runs[st] = L.moments()
     e = _errs(runs[storage], runs["f32"])
     print(f"{storage} D={D}: e_rho={e[0]:.2e} e_u={e[1]:.2e} e_T={e[2]:.2e}", flush=True)
-    assert e[0] < (1e-3 if storage == "f16dev" else 3e-2)
+    assert e[0] < 1e-3
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
@@ -318,26 +325,27 @@ def test_16bit_rereference():
     assert e[0] < 1e-3 and e[0] < e0[0]
 
 
-def test_16bit_long_horizon_3d():
-    """3D droplet (128^3, R = 20, T/Tc = 0.8) after 1e4 steps: FP16 deviation
+@pytest.mark.parametrize("storage", ["f16dev", pytest.param("bf16dev", marks=pytest.mark.skip(reason=BF16_3D))])
+def test_16bit_long_horizon_3d(storage):
+    """3D droplet (128^3, R = 20, T/Tc = 0.8) after 1e4 steps: 16-bit deviation
     storage (re-referenced every 100 steps) stays within 1e-3 of FP32 storage
-    in density (measured 1.1e-4); BF16 is held to 5e-3 (measured 1.5e-3)."""
+    in density (FP16 measured 1.1e-4)."""
     n = 128
     shape = (n, n, n)
     T0 = 0.8 * synth.T_CRIT
     rl, rv, _ = ev.eos_coexistence(T0, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
     rho = synth.droplet(shape, 20.0, rl, rv, noise=1e-4)
     out = {}
-    for st in ("f32", "f16dev", "bf16dev"):
+    for st in ("f32", storage):
         L = ev.Lattice(3, n, n, n, storage=st)
         L.set_params(**P)
         L.init_fields(rho, np.full(shape, T0))
         L.step(10000)
         out[st] = L.moments()[0]
-    for st, bound in (("f16dev", 1e-3), ("bf16dev", 5e-3)):
-        e = np.abs(out[st] - out["f32"]).max() / np.abs(out["f32"]).max()
-        print(f"{st} 128^3 1e4 steps: e_rho {e:.2e}", flush=True)
-        assert e < bound
+        del L
+    e = np.abs(out[storage] - out["f32"]).max() / np.abs(out["f32"]).max()
+    print(f"{storage} 128^3 1e4 steps: e_rho {e:.2e}", flush=True)
+    assert e < 1e-3
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])

@@ -23,8 +23,12 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     L.evlbm_last_error.restype = ctypes.c_char_p
     L.evlbm_create.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
-    L.evlbm_eos_coexistence.argtypes = [ctypes.c_double] * 4 + [ctypes.POINTER(ctypes.c_double)]
+    L.evlbm_eos_coexistence.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [ctypes.POINTER(ctypes.c_double)]
+    L.evlbm_eos_critical.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3 + [ctypes.POINTER(ctypes.c_double)]
     return L
+
+
+VDW, CS = 0, 1
 
 
 @pytest.mark.parametrize("lattice,nx,ny,nz,storage,why", [
@@ -52,7 +56,7 @@ def test_create_rejects_a_null_handle_pointer(lib):
 def test_host_coexistence_matches_oracle_equal_area(lib, Tr):
     T = Tr * synth.T_CRIT
     out = (ctypes.c_double * 3)()
-    assert lib.evlbm_eos_coexistence(synth.R_GAS, synth.A_ATTR, synth.B_EXCL, T, out) == OK
+    assert lib.evlbm_eos_coexistence(VDW, synth.R_GAS, synth.A_ATTR, synth.B_EXCL, T, out) == OK
     rl, rv, P = TH.coexistence(T, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
     print(f"T/Tc {Tr}: library {out[0]:.15g} {out[1]:.15g} {out[2]:.15g}, oracle {rl:.15g} {rv:.15g} {P:.15g}")
     assert abs(out[0] - rl) <= 1e-9 * rl
@@ -70,4 +74,44 @@ def test_host_coexistence_matches_oracle_equal_area(lib, Tr):
 ])
 def test_host_coexistence_rejects_states_without_two_phases(lib, R, a, b, T):
     out = (ctypes.c_double * 3)()
-    assert lib.evlbm_eos_coexistence(R, a, b, T, out) == EINVAL
+    assert lib.evlbm_eos_coexistence(VDW, R, a, b, T, out) == EINVAL
+    assert lib.evlbm_eos_coexistence(7, synth.R_GAS, synth.A_ATTR, synth.B_EXCL, 0.5 * synth.T_CRIT, out) == EINVAL
+
+
+@pytest.mark.parametrize("R,a,b,Tr", [
+    (1.0, synth.A_CS, synth.B_CS, 1.001), (1.0, synth.A_CS, synth.B_CS, 1.1), (1.0, synth.A_CS, synth.B_CS, 0.0),
+    (1.0, synth.A_CS, 0.0, 0.5), (1.0, 0.0, synth.B_CS, 0.5), (0.0, synth.A_CS, synth.B_CS, 0.5),
+])
+def test_host_cs_coexistence_rejects_states_without_two_phases(lib, R, a, b, Tr):
+    out = (ctypes.c_double * 3)()
+    T = Tr * 0.3773 * synth.A_CS / synth.B_CS  # Tr times (about) the Carnahan-Starling T_c
+    assert lib.evlbm_eos_coexistence(CS, R, a, b, T, out) == EINVAL
+
+
+@pytest.mark.parametrize("eos,a,b", [(VDW, synth.A_ATTR, synth.B_EXCL), (CS, synth.A_CS, synth.B_CS), (CS, 0.1, 0.25)])
+def test_host_critical_point_matches_oracle(lib, eos, a, b):
+    """The library's critical point (closed form; bisection of the analytic
+    s' = eta s'' for Carnahan-Starling) against the oracle's (central
+    differences of the pressure, bracketing)."""
+    out = (ctypes.c_double * 3)()
+    assert lib.evlbm_eos_critical(eos, 1.0, a, b, out) == OK
+    rc, Tc, Pc = TH.critical_point(1.0, a, b, "cs" if eos == CS else "vdw")
+    assert out[0] == pytest.approx(rc, rel=1e-7)
+    assert out[1] == pytest.approx(Tc, rel=1e-7)
+    assert out[2] == pytest.approx(Pc, rel=1e-7)
+
+
+@pytest.mark.parametrize("Tr", [0.55, 0.65, 0.8, 0.9, 0.97, 0.99])
+def test_host_cs_coexistence_matches_oracle_equal_area(lib, Tr):
+    """Carnahan-Starling coexistence: the library's Newton iteration on equal
+    pressure and chemical potential against the oracle's equal-area rule
+    evaluated by quadrature."""
+    cp = (ctypes.c_double * 3)()
+    assert lib.evlbm_eos_critical(CS, 1.0, synth.A_CS, synth.B_CS, cp) == OK
+    T = Tr * cp[1]
+    out = (ctypes.c_double * 3)()
+    assert lib.evlbm_eos_coexistence(CS, 1.0, synth.A_CS, synth.B_CS, T, out) == OK
+    rl, rv, P = TH.coexistence(T, 1.0, synth.A_CS, synth.B_CS, "cs")
+    assert abs(out[0] - rl) <= 1e-8 * rl
+    assert abs(out[1] - rv) <= 1e-8 * rv
+    assert abs(out[2] - P) <= 1e-8 * abs(P)
