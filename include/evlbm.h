@@ -145,6 +145,19 @@ int evlbm_read_moments(evlbm_t h, void *rho, void *u, void *T, int where);
  * Blocks.  Errors: ESTATE, EHIP. */
 int evlbm_global_sums(evlbm_t h, double out[8]);
 
+/* The global sums of evlbm_global_sums written to device memory without any
+ * allocation, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): out_dev[8]
+ * (device FP64, caller owned) receives the same values as evlbm_global_sums,
+ * enqueued on the handle's stream (no synchronisation).  The reduction's
+ * partials live in a fixed device array of the library (4 MiB per GPU, held
+ * until the process ends), so lattices of at most 2^24 cells are accepted.
+ * Calls that overlap on one GPU share that array and race: order them (one
+ * stream, or events).  Call with the lattice's device current.
+ * Errors: EINVAL (null argument, more than 2^24 cells, another device
+ * current), ESTATE, EHIP. */
+int evlbm_global_sums_noalloc(evlbm_t h, double *out_dev);
+
 /* FP64 region means for the coexistence (Fig. 1) and Laplace checks.
  * SLAB: geom = {xl0, xl1, xv0, xv1, xv2, xv3}: liquid x in [xl0, xl1),
  *   vapour x in [xv0, xv1) U [xv2, xv3) (all y, z).

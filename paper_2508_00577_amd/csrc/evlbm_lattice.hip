@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -775,6 +776,79 @@ int evlbm_global_sums(evlbm_t h, double out[8])
     if (rc) return rc;
     const int ops[8] = {0, 0, 0, 0, 0, 0, 1, 2};
     return finish_reduce(h, nb, 8, ops, out);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- sums without allocation
+
+// Device scratch of evlbm_global_sums_noalloc: the FP64 block partials of the
+// reduction, 8 values for each block of 256 cells, for lattices of up to
+// NOALLOC_MAX_CELLS cells (4 MiB).  One array per GPU, held until the process
+// ends; host code never names it, only the per-device address that
+// hipGetSymbolAddress returns for it (noalloc_scratch()).
+static constexpr long NOALLOC_MAX_CELLS = 1L << 24;
+static constexpr long NOALLOC_DOUBLES = 8 * (NOALLOC_MAX_CELLS / 256);
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mutex;
+double *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept.
+int noalloc_scratch(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(EVLBM_EINVAL, "device %d beyond the supported range", dev);
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_noalloc_ptr[dev] = (double *)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return EVLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int evlbm_global_sums_noalloc(evlbm_t h, double *out_dev)
+{
+    if (!h || !out_dev) return fail(EVLBM_EINVAL, "null argument");
+    if (!h->initialized) return fail(EVLBM_ESTATE, "lattice not initialised");
+    if (h->N > NOALLOC_MAX_CELLS)
+        return fail(EVLBM_EINVAL, "lattice of %ld cells: the sums without allocation take at most %ld", h->N,
+                    NOALLOC_MAX_CELLS);
+    // the scratch belongs to the device the handle's stream runs on
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != h->device) return fail(EVLBM_EINVAL, "call with the lattice's device (%d) current", h->device);
+    double *partial = nullptr;
+    int rc = noalloc_scratch(&partial);
+    if (rc) return rc;
+    const long nb = (h->N + 255) / 256;
+    // every block writes all of its 8 partials, so nothing needs clearing
+    if (h->walls) {
+        wall_sums(h, partial);
+    } else {
+        refresh_moments(h);
+        dispatch<RunLap>(h);
+        dispatch<RunSums>(h, partial, nb);
+    }
+    rc = check_launch("k_sums");
+    if (rc) return rc;
+    const int4 lo = make_int4(0, 0, 0, 0), hi = make_int4(0, 0, 1, 2);
+    hipLaunchKernelGGL(k_reduce_final, dim3(8), dim3(256), 0, h->stream, (const double *)partial, nb, lo, hi, out_dev);
+    return check_launch("reduce");
 }
 
 int evlbm_measure(evlbm_t h, int kind, const double *geom, double out[8])
