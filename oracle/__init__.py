@@ -63,6 +63,7 @@ def lib():
         L.evo_set_params.argtypes = [ctypes.c_void_p] + [ctypes.c_double] * 7
         L.evo_set_eos.argtypes = [ctypes.c_void_p, ctypes.c_int]
         L.evo_set_walls.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.evo_set_prandtl.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.evo_init.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
         L.evo_get_pops.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.evo_set_pops.argtypes = [ctypes.c_void_p, _dp, _dp]
@@ -179,15 +180,17 @@ class Lattice:
             lib().evo_destroy(h)
             self._h = None
 
-    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0, eos="vdw"):
+    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0, eos="vdw", Pr=1.0):
         """Model parameters; eos selects the contact factor of Enskog's
         pressure: "vdw" (the paper's van der Waals form) or "cs"
-        (Carnahan-Starling)."""
+        (Carnahan-Starling); Pr the Prandtl number (tau_g = tau/Pr)."""
         rc = lib().evo_set_params(self._h, R, a, b, kappa, tau, lam, sphi)
         if rc != 0:
             raise ValueError("invalid parameters")
         if lib().evo_set_eos(self._h, EOS_KINDS[eos]) != 0:
             raise ValueError("unknown eos")
+        if lib().evo_set_prandtl(self._h, float(Pr)) != 0:
+            raise ValueError("Pr must be positive")
 
     def set_walls(self, Tw, Uw, enable=True):
         """Diffuse walls normal to x at x = -1/2 (at rest) and x = nx - 1/2

@@ -8,9 +8,10 @@ momentum balance eq. momentum_balance with T_NS = -mu S and the kinetic
 energy balance eq. LB_energy_balance with k = (5/2) R mu:
   - x-momentum: the pressure P = P_E - a rho^2 is uniform (kappa = 0);
   - y-momentum: mu du/dx = tau_w, a constant;
-  - energy: k dT/dx + mu u du/dx = const, so with mu du/dx = tau_w,
-    (5/2) R dT/du = c - u, and T(0) = T(U_w) = T_w gives
-    T(u) = T_w + u (U_w - u)/(5 R)   (Pr = 1, c_p = 5R/2), whatever mu(rho, T);
+  - energy: k dT/dx + mu u du/dx = const, so with mu du/dx = tau_w and
+    k = c_p mu/Pr (c_p = 5R/2; Pr = 1 in the paper), (c_p/Pr) dT/du = c - u,
+    and T(0) = T(U_w) = T_w gives T(u) = T_w + Pr u (U_w - u)/(5 R),
+    whatever mu(rho, T);
   - rho(u) solves P_E(rho, T(u)) - a rho^2 = P;
   - x(u) = (1/tau_w) int_0^u mu du' with mu = tau P_E (eq. viscosity under
     eq. P0E, dt = 1), tau_w = int_0^U_w mu du / L;
@@ -44,11 +45,11 @@ def sound_speed(rho, RT, a, b, eos="vdw", R=1.0):
     return np.sqrt(Prho + PT * PE / (rho * rho * 1.5 * R))
 
 
-def profile(L, rho_mean, Tw, Uw, a, b, tau, eos="vdw", R=1.0, n=4001):
+def profile(L, rho_mean, Tw, Uw, a, b, tau, eos="vdw", R=1.0, n=4001, Pr=1.0):
     """Steady profile on a fine grid of u in [0, U_w]: dict of arrays x, u, T,
     rho, Mach and the pressure P and wall stress tau_w."""
     us = np.linspace(0.0, Uw, n)
-    T = Tw + us * (Uw - us) / (5.0 * R)
+    T = Tw + Pr * us * (Uw - us) / (5.0 * R)
 
     def fields(P):
         rho = np.array([_rho_at(P, R * t, a, b, eos) for t in T])
@@ -79,13 +80,13 @@ def at(prof, xs):
     return {k: np.interp(xs, prof["x"], prof[k]) for k in ("u", "T", "rho", "Mach")}
 
 
-def wall_speed_for_mach(L, rho_mean, Tw, Ma, a, b, tau, eos="vdw", R=1.0):
+def wall_speed_for_mach(L, rho_mean, Tw, Ma, a, b, tau, eos="vdw", R=1.0, Pr=1.0):
     """U_w that puts the Mach number at the moving wall at Ma (fixed point:
     the wall's density depends on U_w through the heating)."""
     rho = rho_mean
     U = Ma * sound_speed(rho, R * Tw, a, b, eos, R)
     for _ in range(50):
-        pr = profile(L, rho_mean, Tw, U, a, b, tau, eos, R, n=801)
+        pr = profile(L, rho_mean, Tw, U, a, b, tau, eos, R, n=801, Pr=Pr)
         Un = Ma * sound_speed(pr["rho"][-1], R * Tw, a, b, eos, R)
         if abs(Un - U) < 1e-13 * U:
             break

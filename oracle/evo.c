@@ -35,6 +35,15 @@
  *     chi = (1 - eta/2)/(1 - eta)^3 with eta = b rho/4 (Carnahan & Starling,
  *     J. Chem. Phys. 51, 635 (1969)).  Either way P_E = rho R T Z(rho) and
  *     gamma_0 of eq. gamma follows from Z.
+ *   - Prandtl number (optional; the concluding paragraph names a
+ *     quasi-equilibrium relaxation of g as the way to lift Pr = 1, the paper
+ *     gives no scheme).  g relaxes with beta_g = 1/(2 tau_g + 1), tau_g =
+ *     tau/Pr, in both terms of eq. pre_LBM, and the part of its energy flux
+ *     that carries the viscous heating, u . Pi^neq with Pi^neq the second
+ *     moment of fh - f^eq, keeps f's beta through the quasi-equilibrium term
+ *     2 (beta_g - beta) dg, dg_i = (1/2) c_i . (u . Pi^neq) on the axis
+ *     directions (zero mass and energy, flux u . Pi^neq).  Pr = 1 is the
+ *     paper's scheme exactly; k = (5/2) R mu/Pr.
  *   - Walls (the thermal Couette flow after eq. P0E, Fig. 2; optional, normal
  *     to x at x = -1/2 and x = nx - 1/2, the second moving with U_w along y,
  *     both at T_w): diffuse reflection.  A population entering the fluid from
@@ -62,6 +71,7 @@ typedef struct {
     double w[QMAX];
     /* model parameters */
     double R, a, b, kappa, tau, lambda, sphi;
+    double prandtl; /* tau/tau_g of the energy populations (1: the paper's scheme) */
     int eos; /* 0: van der Waals contact factor, 1: Carnahan-Starling */
     int walls;       /* 1: diffuse walls normal to x (see the header) */
     double Tw, Uw;   /* wall temperature, speed of the wall at x = nx - 1/2 (along y) */
@@ -291,6 +301,7 @@ evo_t *evo_create(int D, int nx, int ny, int nz)
     h->tau = 1.0;
     h->lambda = 1.0;
     h->sphi = -1.0;
+    h->prandtl = 1.0;
     long N = h->N, Q = h->Q;
     h->f = alloc_field(Q * N);
     h->g = alloc_field(Q * N);
@@ -366,6 +377,14 @@ int evo_set_params(evo_t *h, double R, double a, double b, double kappa,
     h->tau = tau;
     h->lambda = lambda;
     h->sphi = sphi;
+    return 0;
+}
+
+/* Prandtl number Pr = tau/tau_g of the energy populations (see the header). */
+int evo_set_prandtl(evo_t *h, double Pr)
+{
+    if (!(Pr > 0)) return -1;
+    h->prandtl = Pr;
     return 0;
 }
 
@@ -621,6 +640,8 @@ static void stage_collide(evo_t *h, double *diag)
     int D = h->D;
     double beta = 1.0 / (2.0 * h->tau + 1.0);
     double wstar = (1.0 / h->lambda) * (1.0 - beta);
+    double beta_g = 1.0 / (2.0 * (h->tau / h->prandtl) + 1.0);
+    double wstar_g = (1.0 / h->lambda) * (1.0 - beta_g);
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < N; x++) {
         double r = h->rho[x];
@@ -634,6 +655,14 @@ static void stage_collide(evo_t *h, double *diag)
             zst[a] = h->Th[x] + us[a] * us[a] + h->lambda * h->Phi[a * N + x] / r;
         }
         double sf = 0, sg = 0, scf[3] = {0, 0, 0};
+        /* u . Pi^neq with Pi^neq = sum_i c_i c_i (fh_i - f^eq_i) (quasi-equilibrium flux) */
+        double upi[3] = {0, 0, 0};
+        for (int i = 0; i < h->Q; i++) {
+            double d = h->fh[i * N + x] - product_population(h, i, r, u, zeq);
+            double cu = 0.0;
+            for (int a = 0; a < D; a++) cu += (double)h->c[i][a] * u[a];
+            for (int a = 0; a < D; a++) upi[a] += (double)h->c[i][a] * cu * d;
+        }
         for (int i = 0; i < h->Q; i++) {
             double feq = product_population(h, i, r, u, zeq);
             double fst = product_population(h, i, r, us, zst);
@@ -647,8 +676,11 @@ static void stage_collide(evo_t *h, double *diag)
                 gst += 0.5 * cq;
             }
             double fh = h->fh[i * N + x], gh = h->gh[i * N + x];
+            double dg = 0.0;
+            if (c2 == 1)
+                for (int a = 0; a < D; a++) dg += 0.5 * (double)h->c[i][a] * upi[a];
             double fn = fh + 2.0 * beta * (feq - fh) + wstar * (fst - feq);
-            double gn = gh + 2.0 * beta * (geq - gh) + wstar * (gst - geq);
+            double gn = gh + 2.0 * beta_g * (geq - gh) + wstar_g * (gst - geq) + 2.0 * (beta_g - beta) * dg;
             h->f[i * N + x] = fn;
             h->g[i * N + x] = gn;
             if (diag) {
