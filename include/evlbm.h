@@ -66,6 +66,12 @@ enum {
     EVLBM_OPT_USE_GRAPH = 5,   /* 1: replay step chunks from a captured hipGraph (default 1) */
     EVLBM_OPT_REREF_EVERY = 6, /* 16-bit storage: re-reference every K steps (0 = never; default 100) */
     EVLBM_OPT_EOS = 8,         /* contact factor of Enskog's pressure: EVLBM_EOS_VDW (default) or EVLBM_EOS_CS */
+    EVLBM_OPT_PRANDTL = 9,     /* Prandtl number Pr > 0 (default 1, the paper's scheme; the concluding paragraph
+                                  names a quasi-equilibrium relaxation of g for other values, the scheme is this
+                                  library's): g relaxes with tau_g = tau/Pr in both terms of eq. pre_LBM and keeps
+                                  f's relaxation for its viscous-heating flux u . Pi^neq (Pi^neq = sum c c
+                                  (fh - f^eq)) through a zero-mass, zero-energy term on the axis directions; then
+                                  k = (5/2) R mu/Pr.  Pr != 1 takes the two-pass D3Q27 step. */
     EVLBM_OPT_PUSH_MOMENTS = 7 /* 1 = one-pass step (default), 0 = two-pass step, where the moments are pulled
                                   again before each collision.  D3Q27 with FP32 or FP64 storage: the collision
                                   pushes the next moments (16-bit D3Q27 storage is always two-pass).  D2Q9:
@@ -177,7 +183,7 @@ int evlbm_get_populations(evlbm_t h, void *f, void *g, int where);
 int evlbm_set_populations(evlbm_t h, const void *f, const void *g, int where);
 
 /* Bit-exact dump of the stored populations, dense [2Q][N], after a one-line
- * JSON header (format evlbm-4: lattice, storage, sizes, parameters, step,
+ * JSON header (format evlbm-5: lattice, storage, sizes, parameters incl. the pressure closure, Prandtl number and walls, step,
  * byte counts), followed for 16-bit storage by the per-cell reference state
  * as four FP32 values per cell, and for the one-pass D3Q27 step by the
  * moment field rho, j, e ([D+2][N] in the arithmetic precision), which that
@@ -262,8 +268,8 @@ int evlbm_batch_destroy(evlbm_batch_t b);
 int evlbm_batch_set_params(evlbm_batch_t b, double R, double a, double bexcl, double kappa, double tau,
                            double lambda, double sphi);
 
-/* Batch options: EVLBM_OPT_SPHI, EVLBM_OPT_REREF_EVERY and EVLBM_OPT_EOS, as on a
- * lattice, shared by every domain.  Errors: EINVAL (other keys, bad values). */
+/* Batch options: EVLBM_OPT_SPHI, EVLBM_OPT_REREF_EVERY and EVLBM_OPT_EOS, as on
+ * a lattice, shared by every domain (EVLBM_OPT_PRANDTL accepts only 1).  Errors: EINVAL (other keys, bad values). */
 int evlbm_batch_set_option(evlbm_batch_t b, int key, double value);
 
 /* Initialise domain k from host FP64 fields rho[N_k], u[2 N_k] (nullable), T[N_k].

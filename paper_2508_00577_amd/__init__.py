@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libevlbm.so")
 D2Q9, D3Q27 = 2, 3
 F64, F32, F16DEV, BF16DEV = 0, 1, 2, 3
 HOST_F64, DEVICE_F32, DEVICE_F64 = 0, 1, 2
-OPT_SPHI, OPT_CHECK_EVERY, OPT_USE_GRAPH, OPT_REREF_EVERY, OPT_PUSH_MOMENTS, OPT_EOS = 1, 4, 5, 6, 7, 8
+OPT_SPHI, OPT_CHECK_EVERY, OPT_USE_GRAPH, OPT_REREF_EVERY, OPT_PUSH_MOMENTS, OPT_EOS, OPT_PRANDTL = 1, 4, 5, 6, 7, 8, 9
 EOS = {"vdw": 0, "cs": 1}  # contact factor of Enskog's pressure: van der Waals, Carnahan-Starling
 MEASURE_SLAB, MEASURE_DROPLET = 1, 2
 STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, "bf16dev": BF16DEV}
@@ -186,11 +186,12 @@ class Lattice:
     def set_relaxation(self, tau=1.0, lam=1.0):
         _check(lib().evlbm_set_relaxation(self._h, tau, lam))
 
-    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0, eos="vdw"):
+    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0, eos="vdw", Pr=1.0):
         self.set_eos(R, a, b, kappa)
         self.set_relaxation(tau, lam)
         self.set_option(OPT_SPHI, sphi)
         self.set_option(OPT_EOS, EOS[eos])
+        self.set_option(OPT_PRANDTL, Pr)
 
     def set_option(self, key, value):
         _check(lib().evlbm_set_option(self._h, int(key), float(value)))

@@ -102,6 +102,7 @@ struct evlbm_batch {
     int variant = 0;
     double R = 1.0, a = 0.0, b = 0.0, kappa = 0.0, tau = 1.0, lambda = 1.0, sphi = -1.0;
     int eos = EVLBM_EOS_VDW;
+    double prandtl = 1.0;
     int cur = 0;
     int64_t step = 0;
     int64_t reref_every = 100;  // 16-bit storage: re-reference period in steps (as a lattice's default)
@@ -138,7 +139,7 @@ int scratch(evlbm_batch *b, size_t bytes)
 template <typename R>
 StepParams<R> bparams(const evlbm_batch *b)
 {
-    StepParams<R> p = model_params<R>(b->eos, b->R, b->a, b->b, b->kappa, b->tau, b->lambda, b->sphi);
+    StepParams<R> p = model_params<R>(b->eos, b->R, b->a, b->b, b->kappa, b->tau, b->lambda, b->sphi, b->prandtl);
     p.refst = b->refst;
     return p;
 }
@@ -415,6 +416,9 @@ int evlbm_batch_set_option(evlbm_batch_t b, int key, double value)
     case EVLBM_OPT_EOS:
         if (value != EVLBM_EOS_VDW && value != EVLBM_EOS_CS) return fail(EVLBM_EINVAL, "unknown pressure closure");
         b->eos = (int)value;
+        break;
+    case EVLBM_OPT_PRANDTL:
+        if (value != 1.0) return fail(EVLBM_EINVAL, "the batch runs at Prandtl number 1 (set Pr on a lattice)");
         break;
     default:
         return fail(EVLBM_EINVAL, "option %d is not a batch option", key);

@@ -24,6 +24,7 @@ struct evlbm_lattice {
     // model
     double R = 1.0, a = 0.0, b = 0.0, kappa = 0.0, tau = 1.0, lambda = 1.0, sphi = -1.0;
     int eos = EVLBM_EOS_VDW;
+    double prandtl = 1.0;               // Pr = tau/tau_g of the energy populations
     // diffuse walls normal to x (evlbm_set_walls): temperature, speed of the
     // wall at x = nx - 1/2, work buffers of the wall step (streamed
     // populations [2Q][N], fields [3D + 2][N], arithmetic precision)

@@ -46,7 +46,7 @@ size_t real_bytes(int storage) { return storage == EVLBM_F64 ? 8 : 4; }
 template <typename R>
 StepParams<R> make_params(const evlbm_lattice *h)
 {
-    StepParams<R> p = model_params<R>(h->eos, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi);
+    StepParams<R> p = model_params<R>(h->eos, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi, h->prandtl);
     p.nx = h->nx;
     p.ny = h->ny;
     p.nz = h->nz;
@@ -102,14 +102,40 @@ struct Ops {
         const int nbx = (h->nx + TX - 1) / TX, nby = (h->ny + TY - 1) / TY, nbz = (h->nz + ZC - 1) / ZC;
         R *mn = PUSH ? (R *)h->m_alt : nullptr, *sh = PUSH ? (R *)h->shell : nullptr;
         // buffer addressing while every offset into one population (f or g) stays below 2^32
-        if ((double)27 * h->ds * sizeof(T) < 4294967296.0)
-            hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true, PUSH>), dim3(nbx * nby * nbz), dim3(TX, TY), 0,
-                               h->stream, (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby,
-                               mn, sh);
+        const bool buf = (double)27 * h->ds * sizeof(T) < 4294967296.0;
+        const dim3 g(nbx * nby * nbz), b(TX, TY);
+        if constexpr (!PUSH) {
+            // Prandtl number != 1: the kernels with the quasi-equilibrium term
+            if (h->prandtl != 1.0) {
+                if (buf)
+                    hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true, false, true>), g, b, 0, h->stream,
+                                       (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
+                else
+                    hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, false, false, true>), g, b, 0, h->stream,
+                                       (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
+                return;
+            }
+        }
+        if constexpr (PUSH) {
+            // the one-pass step, the benchmark's kernel: the pressure closure
+            // is compiled in rather than branched on per cell
+            if (buf && h->eos == EVLBM_EOS_VDW)
+                hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true, true, false, EVLBM_EOS_VDW>), g, b, 0, h->stream,
+                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
+            else if (buf)
+                hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true, true, false, EVLBM_EOS_CS>), g, b, 0, h->stream,
+                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
+            else
+                hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, false, true>), g, b, 0, h->stream, (const T *)src,
+                                   (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
+            return;
+        }
+        if (buf)
+            hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true, PUSH>), g, b, 0, h->stream, (const T *)src, (T *)dst,
+                               (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
         else
-            hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, false, PUSH>), dim3(nbx * nby * nbz), dim3(TX, TY), 0,
-                               h->stream, (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby,
-                               mn, sh);
+            hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, false, PUSH>), g, b, 0, h->stream, (const T *)src, (T *)dst,
+                               (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
     }
 
     // D3Q27 one-pass step: collision pushing the next moments into m_alt and
@@ -135,7 +161,10 @@ struct Ops {
             // pulled populations in the collision itself (no moment pass)
             const int nbx = (h->nx + BX - 1) / BX, nby = (h->ny + BY - 1) / BY, nbz = (h->nz + BZ - 1) / BZ;
             const int nt = nbx * nby * nbz;
-            if (h->push)
+            if (h->prandtl != 1.0)
+                hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ, true, true>), dim3(nt), dim3(BX, BY, BZ), 0, h->stream,
+                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, nt);
+            else if (h->push)
                 hipLaunchKernelGGL((k_collide<D, S, BX, BY, BZ, true>), dim3(nt), dim3(BX, BY, BZ), 0, h->stream,
                                    (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, nt);
             else
@@ -359,7 +388,10 @@ int scan_nonfinite(evlbm_lattice *h)
 }
 
 // Does the step push the next moments (D3Q27 one-pass step)?
-static bool pushes(const evlbm_lattice *h) { return h->D == 3 && h->push && h->shell != nullptr && !h->walls; }
+static bool pushes(const evlbm_lattice *h)
+{
+    return h->D == 3 && h->push && h->shell != nullptr && !h->walls && h->prandtl == 1.0;
+}
 // the one-pass D2Q9 step: the collision sums its halo's moments itself
 static bool fused(const evlbm_lattice *h) { return h->D == 2 && h->push && !h->walls; }
 
@@ -595,6 +627,11 @@ int evlbm_set_option(evlbm_t h, int key, double value)
     case EVLBM_OPT_EOS:
         if (value != EVLBM_EOS_VDW && value != EVLBM_EOS_CS) return fail(EVLBM_EINVAL, "unknown pressure closure");
         h->eos = (int)value;
+        break;
+    case EVLBM_OPT_PRANDTL:
+        if (!(value > 0) || !std::isfinite(value)) return fail(EVLBM_EINVAL, "the Prandtl number must be positive");
+        h->prandtl = value;
+        h->m_valid = false;
         break;
     default:
         return fail(EVLBM_EINVAL, "unknown option %d", key);
@@ -956,10 +993,10 @@ int evlbm_checkpoint_save(evlbm_t h, const char *path)
     int n = snprintf(hdr, sizeof(hdr),
                      "{\"format\":\"evlbm-5\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%.17g,\"a\":%.17g,\"b\":%.17g,\"kappa\":%.17g,\"tau\":%.17g,\"lambda\":%.17g,"
-                     "\"sphi\":%.17g,\"eos\":%d,\"walls\":%d,\"Tw\":%.17g,\"Uw\":%.17g,\"step\":%lld,"
-                     "\"bytes\":%zu,\"moment_bytes\":%zu}\n",
+                     "\"sphi\":%.17g,\"eos\":%d,\"Pr\":%.17g,\"walls\":%d,\"Tw\":%.17g,\"Uw\":%.17g,"
+                     "\"step\":%lld,\"bytes\":%zu,\"moment_bytes\":%zu}\n",
                      h->D, h->nx, h->ny, h->nz, h->storage, h->R, h->a, h->b, h->kappa, h->tau, h->lambda, h->sphi,
-                     h->eos, h->walls ? 1 : 0, h->Tw, h->Uw, (long long)h->step, bytes, m_bytes);
+                     h->eos, h->prandtl, h->walls ? 1 : 0, h->Tw, h->Uw, (long long)h->step, bytes, m_bytes);
     bool ok = fwrite(hdr, 1, n, fp) == (size_t)n && fwrite(host.data(), 1, bytes, fp) == bytes;
     if (ok && h->refst) {  // the 16-bit reference state of every cell
         std::vector<float4> r((size_t)h->N);
@@ -983,18 +1020,18 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
         return fail(EVLBM_EIO, "empty checkpoint %s", path);
     }
     int D = 0, nx = 0, ny = 0, nz = 0, st = -1, eos = 0, walls = 0;
-    double Tw = 0.0, Uw = 0.0;
+    double Tw = 0.0, Uw = 0.0, Pr = 1.0;
     long long step = 0;
     double R, a, b, kappa, tau, lam, sphi;
     size_t bytes = 0, m_bytes = 0;
     int got = sscanf(hdr,
                      "{\"format\":\"evlbm-5\",\"lattice\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"storage\":%d,"
                      "\"R\":%lg,\"a\":%lg,\"b\":%lg,\"kappa\":%lg,\"tau\":%lg,\"lambda\":%lg,"
-                     "\"sphi\":%lg,\"eos\":%d,\"walls\":%d,\"Tw\":%lg,\"Uw\":%lg,\"step\":%lld,"
+                     "\"sphi\":%lg,\"eos\":%d,\"Pr\":%lg,\"walls\":%d,\"Tw\":%lg,\"Uw\":%lg,\"step\":%lld,"
                      "\"bytes\":%zu,\"moment_bytes\":%zu}",
-                     &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &eos, &walls, &Tw, &Uw, &step, &bytes,
-                     &m_bytes);
-    if (got != 19 || (eos != EVLBM_EOS_VDW && eos != EVLBM_EOS_CS)) {
+                     &D, &nx, &ny, &nz, &st, &R, &a, &b, &kappa, &tau, &lam, &sphi, &eos, &Pr, &walls, &Tw, &Uw, &step,
+                     &bytes, &m_bytes);
+    if (got != 20 || (eos != EVLBM_EOS_VDW && eos != EVLBM_EOS_CS) || !(Pr > 0)) {
         fclose(fp);
         return fail(EVLBM_EIO, "bad checkpoint header in %s", path);
     }
@@ -1035,6 +1072,7 @@ int evlbm_checkpoint_load(evlbm_t h, const char *path)
     h->lambda = lam;
     h->sphi = sphi;
     h->eos = eos;
+    h->prandtl = Pr;
     if (walls) {
         const int rcw = evlbm_set_walls(h, 1, Tw, Uw);
         if (rcw) return rcw;

@@ -8,7 +8,7 @@ namespace evlbm {
 
 template <typename R>
 inline StepParams<R> model_params(int eos, double Rg, double a, double b, double kappa, double tau, double lambda,
-                                  double sphi)
+                                  double sphi, double prandtl = 1.0)
 {
     StepParams<R> p;
     p.nx = p.ny = p.nz = 1;
@@ -21,6 +21,12 @@ inline StepParams<R> model_params(int eos, double Rg, double a, double b, double
     const double beta = 1.0 / (2.0 * tau + 1.0);  // eq. beta with dt = 1
     p.two_beta = (R)(2.0 * beta);
     p.wstar = (R)((1.0 / lambda) * (1.0 - beta));
+    // energy populations relax with tau_g = tau/Pr (Pr = 1: the same beta)
+    const double beta_g = prandtl == 1.0 ? beta : 1.0 / (2.0 * tau / prandtl + 1.0);
+    p.two_beta_g = (R)(2.0 * beta_g);
+    p.wstar_g = (R)((1.0 / lambda) * (1.0 - beta_g));
+    p.qe = (R)(2.0 * (beta_g - beta));
+    p.vpr = prandtl != 1.0 ? 1 : 0;
     p.lambda = (R)lambda;
     p.sphi = (R)sphi;
     p.Rgas = (R)Rg;

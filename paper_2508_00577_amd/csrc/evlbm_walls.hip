@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(256) k_wall_fields(const R *__restrict__ m, co
 // Corrections (eq. correction_u, correction_gamma, correction_q) with the
 // wall ghosts, then the shifted state, equilibria and update of eq. pre_LBM
 // (collide_pulled) from the streamed populations fh into dst.
-template <int D, int S>
+template <int D, int S, bool VPR>
 __global__ void __launch_bounds__(256) k_wall_collide(const RealT<S> *__restrict__ fh, const RealT<S> *__restrict__ m,
                                                       const RealT<S> *__restrict__ fld, StoreT<S> *__restrict__ dst,
                                                       StepParams<RealT<S>> p)
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(256) k_wall_collide(const RealT<S> *__restrict
         o.oz[k] = 0u;
     }
     const PtrPops<T> pops{dst, dst, p.ds};
-    collide_pulled<D, S>(fr, gr, pops, p, o, rho, inv_rho, K, ez.Z, theta, u, F, Phi, qp);
+    collide_pulled<D, S, PtrPops<T>, NoSink, VPR>(fr, gr, pops, p, o, rho, inv_rho, K, ez.Z, theta, u, F, Phi, qp);
 }
 
 template <int D, typename R, typename O>
@@ -345,8 +345,14 @@ struct WallOps {
     static void step(evlbm_lattice *h)
     {
         analyse(h);
-        hipLaunchKernelGGL((k_wall_collide<D, S>), dim3(blocks(h)), dim3(256), 0, h->stream, (const R *)h->wall_fh,
-                           (const R *)h->m, (const R *)h->wall_fld, (T *)h->buf[1 - h->cur], make_params<R>(h));
+        if (h->prandtl != 1.0)
+            hipLaunchKernelGGL((k_wall_collide<D, S, true>), dim3(blocks(h)), dim3(256), 0, h->stream,
+                               (const R *)h->wall_fh, (const R *)h->m, (const R *)h->wall_fld, (T *)h->buf[1 - h->cur],
+                               make_params<R>(h));
+        else
+            hipLaunchKernelGGL((k_wall_collide<D, S, false>), dim3(blocks(h)), dim3(256), 0, h->stream,
+                               (const R *)h->wall_fh, (const R *)h->m, (const R *)h->wall_fld, (T *)h->buf[1 - h->cur],
+                               make_params<R>(h));
     }
     template <typename O>
     static void readout(evlbm_lattice *h, O *rho, O *u, O *T0)

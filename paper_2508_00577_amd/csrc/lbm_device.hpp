@@ -126,6 +126,10 @@ struct StepParams {
     R a, b, kappa;   // EOS: P_E = rho RT Z(rho) (b: excluded volume), P_V = -a rho^2, capillarity
     R two_beta;      // 2 beta, beta = 1/(2 tau + 1)
     R wstar;         // (dt/lambda)(1 - beta)
+    R two_beta_g;    // the same for the energy populations, beta_g = 1/(2 tau/Pr + 1)
+    R wstar_g;       // (dt/lambda)(1 - beta_g)
+    R qe;            // 2 (beta_g - beta): weight of the quasi-equilibrium flux term (0 at Pr = 1)
+    int vpr;         // 1 when Pr != 1 (the quasi-equilibrium pre-pass runs)
     R lambda, sphi;
     R Rgas;
     const float4 *refst;  // 16-bit deviation storage: reference state of every cell (ref_state_of)
@@ -163,6 +167,14 @@ __device__ inline Enskog<R> enskog(int eos, R b, R rho)
     }
     const R Z = rcp(R(1) - b * rho);
     return Enskog<R>{Z, (R(5) / R(3)) * (R(1) - Z)};
+}
+
+// The same with the closure fixed at compile time (EOSK = EVLBM_EOS_VDW or
+// EVLBM_EOS_CS) or, for EOSK < 0, taken from eos at run time.
+template <int EOSK, typename R>
+__device__ inline Enskog<R> enskog_k(int eos, R b, R rho)
+{
+    return enskog<R>(EOSK < 0 ? eos : EOSK, b, rho);
 }
 
 // FP64 form for initialisation, validation and measurement (exact divisions);

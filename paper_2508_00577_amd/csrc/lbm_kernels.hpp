@@ -237,11 +237,18 @@ struct NoSink {
 
 // Equilibria (eq. feq, f_star, geq, gstar with eq. g_corr), shifted state
 // (eq. def_ustar with Qtilde = 0) and the update eq. pre_LBM for one cell,
+// f with beta and g with beta_g (Prandtl number Pr = tau/tau_g; Pr = 1 is the
+// paper's scheme).  For Pr != 1 (the VPR kernels) g also relaxes its
+// viscous-heating flux with f's beta through a quasi-equilibrium term
+// qe dg, qe = 2 (beta_g - beta), dg_i = (1/2) c_i . (u . Pi^neq) on the axis
+// directions, Pi^neq = sum_i c_i c_i (fh_i - f^eq_i): the Fourier flux then
+// scales with tau_g and the viscous heating with tau (k = (5/2) R mu/Pr),
+// mass and energy unchanged;
 // from its pulled populations (raw stored values fr, gr of pull_pops) into
 // the destination of the accessor at the cell itself (o.ox[1] + o.oy[1] +
 // o.oz[1]).  zf = Z(rho) = P_E/(rho R T) (enskog).  Every stored direction is also handed
 // to sink, decoded.
-template <int D, int S, class A, class Sink = NoSink>
+template <int D, int S, class A, class Sink = NoSink, bool VPR = false>
 __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[], const A &pops,
                                       const StepParams<RealT<S>> &p, const PullOffsets &o, RealT<S> rho,
                                       RealT<S> inv_rho, RealT<S> K, RealT<S> zf, RealT<S> theta,
@@ -282,7 +289,23 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
     const R hE = K;
     const R omb = R(1) - p.two_beta;
     const R c_eq = p.two_beta - p.wstar;
+    const R omb_g = R(1) - p.two_beta_g;
+    const R c_eq_g = p.two_beta_g - p.wstar_g;
     const unsigned cell = o.ox[1] + o.oy[1] + o.oz[1];
+    // u . Pi^neq of the pulled f (quasi-equilibrium flux, Pr != 1 only)
+    R upi[3] = {R(0), R(0), R(0)};
+    if constexpr (VPR) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int kx = cx_of(i) + 1, ky = cy_of(i) + 1, kz = cz_d<D>(i) + 1;
+            const unsigned s = o.ox[kx] + o.oy[ky] + o.oz[kz];
+            const R d = Codec<S>::dec(fr[i], ref_at_b<D, S>(p, i, s)) - rho * fe[0][kx] * fe[1][ky] * fe[2][kz];
+            const R cu = R(cx_of(i)) * u[0] + R(cy_of(i)) * u[1] + R(cz_d<D>(i)) * u[2];
+            upi[0] += R(cx_of(i)) * cu * d;
+            upi[1] += R(cy_of(i)) * cu * d;
+            upi[2] += R(cz_d<D>(i)) * cu * d;
+        }
+    }
 
     // The collision conserves mass and energy exactly: sum f_new = sum fh and
     // sum g_new = sum gh + u.F (eq. pre_LBM with eq. u_shift, T_shift and
@@ -320,11 +343,15 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
                              fe[0][kx] * (xe[1][ky] * fe[2][kz] + fe[1][ky] * xe[2][kz]));
         R gst = rho * ((hS * gs[0][kx] + xs[0][kx]) * (gs[1][ky] * gs[2][kz]) +
                        gs[0][kx] * (xs[1][ky] * gs[2][kz] + gs[1][ky] * xs[2][kz]));
-        if (cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_d<D>(i) * cz_d<D>(i) == 1)
+        R gqe = R(0);
+        if (cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i) + cz_d<D>(i) * cz_d<D>(i) == 1) {
             gst += R(0.5) * (R(cx_of(i)) * qp[0] + R(cy_of(i)) * qp[1] + R(cz_d<D>(i)) * qp[2]);
-        // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq)
+            if (VPR) gqe = R(0.5) * p.qe * (R(cx_of(i)) * upi[0] + R(cy_of(i)) * upi[1] + R(cz_d<D>(i)) * upi[2]);
+        }
+        // eq. pre_LBM: f + 2 beta (f^eq - f) + (dt/lambda)(1 - beta)(f* - f^eq),
+        // g the same with beta_g (plus the quasi-equilibrium term for Pr != 1)
         const R fn = omb * fh + c_eq * feq + p.wstar * fst;
-        const R gn = omb * gh + c_eq * geq + p.wstar * gst;
+        const R gn = VPR ? omb_g * gh + c_eq_g * geq + p.wstar_g * gst + gqe : omb_g * gh + c_eq_g * geq + p.wstar_g * gst;
         mass.add(fh);
         energy.add(gh);
         if (i == SA) {
@@ -367,7 +394,7 @@ __device__ inline void collide_pulled(const StoreT<S> fr[], const StoreT<S> gr[]
 }
 
 // Pull and collide one cell (x, y, z) from src into dst.
-template <int D, int S>
+template <int D, int S, bool VPR = false>
 __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
                                     const StepParams<RealT<S>> &p, int x, int y, int z, RealT<S> rho,
                                     RealT<S> inv_rho, RealT<S> K, RealT<S> RT, RealT<S> zf, RealT<S> theta,
@@ -380,7 +407,8 @@ __device__ inline void collide_cell(const StoreT<S> *__restrict__ src, StoreT<S>
     const PtrPops<StoreT<S>> pops{src, dst, p.ds};
     StoreT<S> fr[Q], gr[Q];
     pull_pops<D, S>(pops, o, fr, gr);
-    collide_pulled<D, S>(fr, gr, pops, p, o, rho, inv_rho, K, zf, theta, u, F, Phi, qp);
+    collide_pulled<D, S, PtrPops<StoreT<S>>, NoSink, VPR>(fr, gr, pops, p, o, rho, inv_rho, K, zf, theta, u, F, Phi,
+                                                          qp);
 }
 
 // ------------------------------------------------------------ k_collide
@@ -418,7 +446,7 @@ struct TileShape {
 // read from m (not used), so the step needs no moment pass: rho and j from
 // one pull of f in the rho stage (j kept in LDS for tile + 1), e from a pull
 // of g in the field stage.
-template <int D, int S, int BX, int BY, int BZ, bool FUSED = false>
+template <int D, int S, int BX, int BY, int BZ, bool FUSED = false, bool VPR = false>
 __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst,
                                      const RealT<S> *__restrict__ m, const StepParams<RealT<S>> &p, int x0, int y0,
                                      int z0)
@@ -547,17 +575,18 @@ __device__ inline void collide_block(const StoreT<S> *__restrict__ src, StoreT<S
         Phi[2] = p.sphi * lds_grad<D, 2, R>(s_f1 + (F_M + 2) * TS::N1, c1, SY, SZ) + Phip;
         qp[2] = p.lambda * (P0 * lds_grad<D, 2, R>(s_f1 + F_TD * TS::N1, c1, SY, SZ) + u[2] * Phip);
     }
-    collide_cell<D, S>(src, dst, p, x, y, z, rho, inv_rho, K, RT, ez.Z, theta, u, F, Phi, qp);
+    collide_cell<D, S, VPR>(src, dst, p, x, y, z, rho, inv_rho, K, RT, ez.Z, theta, u, F, Phi, qp);
 }
 
 // One tile per workgroup, nbx x nby x nbz tiles in XCD order (xcd_tile).
-template <int D, int S, int BX, int BY, int BZ, bool FUSED = false>
+template <int D, int S, int BX, int BY, int BZ, bool FUSED = false, bool VPR = false>
 __global__ void __launch_bounds__(BX *BY *BZ)
     k_collide(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
               StepParams<RealT<S>> p, int nbx, int nby, int ntiles)
 {
     const int t = xcd_tile(blockIdx.x, ntiles), bxy = t % (nbx * nby);
-    collide_block<D, S, BX, BY, BZ, FUSED>(src, dst, m, p, (bxy % nbx) * BX, (bxy / nbx) * BY, (t / (nbx * nby)) * BZ);
+    collide_block<D, S, BX, BY, BZ, FUSED, VPR>(src, dst, m, p, (bxy % nbx) * BX, (bxy / nbx) * BY,
+                                                (t / (nbx * nby)) * BZ);
 }
 
 // ------------------------------------------------------- k_collide_zm (3D)
@@ -717,7 +746,7 @@ __device__ inline R from_right(R v, int tx)
 // also writes the next step's moments: the chunk's own part into m_next,
 // the rest into its shell (slots of Shell, 5 moments per tile, tiles in
 // their natural order); k_push_fixup completes m_next.
-template <int S, int TX, int TY, int ZC, bool BUF, bool PUSH>
+template <int S, int TX, int TY, int ZC, bool BUF, bool PUSH, bool VPR = false, int EOSK = -1>
 __global__ void __launch_bounds__(TX *TY)
     k_collide_zm(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
                  StepParams<RealT<S>> p, int nbx, int nby, RealT<S> *__restrict__ m_next,
@@ -878,7 +907,7 @@ __global__ void __launch_bounds__(TX *TY)
                 }
                 const R K = (mv[j][3] + R(0.5) * uF) * ir - R(0.5) * u2;
                 const R RT = K * (R(2) / R(3));
-                const R theta = RT * enskog(p.eos, p.b, rho).Z;
+                const R theta = RT * enskog_k<EOSK>(p.eos, p.b, rho).Z;
                 const int c1 = lx + ZT::R1X * ly;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
@@ -1172,7 +1201,7 @@ __global__ void __launch_bounds__(TX *TY)
             const R inv_rho = rcp(rho);
             const R K = Kc;
             const R RT = K * (R(2) / R(3));
-            const Enskog<R> ez = enskog(p.eos, p.b, rho);
+            const Enskog<R> ez = enskog_k<EOSK>(p.eos, p.b, rho);
             const R theta = RT * ez.Z;
             const R P0 = rho * theta;
             R u[3], F[3];
@@ -1192,14 +1221,18 @@ __global__ void __launch_bounds__(TX *TY)
             qp[0] = p.lambda * (P0 * ring_grad<0, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[0] * Phip);
             qp[1] = p.lambda * (P0 * ring_grad<1, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[1] * Phip);
             qp[2] = p.lambda * (P0 * ring_grad<2, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[2] * Phip);
-            if constexpr (PUSH)
-                collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, ez.Z, theta, u, F, Phi, qp,
-                                     [&](int i, R f, R g) {
-                                         vf[i] = f;
-                                         vg[i] = g;
-                                     });
-            else
-                collide_pulled<D, S>(fr, gr, pops, p, po, rho, inv_rho, K, ez.Z, theta, u, F, Phi, qp);
+            if constexpr (PUSH) {
+                // the one-pass step runs at Pr = 1 only (the host takes the
+                // two-pass step otherwise): no quasi-equilibrium pre-pass
+                auto push_sink = [&](int i, R f, R g) {
+                    vf[i] = f;
+                    vg[i] = g;
+                };
+                collide_pulled<D, S, Pops, decltype(push_sink), false>(fr, gr, pops, p, po, rho, inv_rho, K, ez.Z,
+                                                                       theta, u, F, Phi, qp, push_sink);
+            } else
+                collide_pulled<D, S, Pops, NoSink, VPR>(fr, gr, pops, p, po, rho, inv_rho, K, ez.Z, theta, u, F, Phi,
+                                                        qp);
         }
         load_fields(k + 1, rvn, mvn);
         pull_pops<3, S>(pops, pull_offsets<3, (int)sizeof(T)>(p.nx, p.ny, p.nz, xl, yl, k + 1), fr, gr);
