@@ -139,6 +139,112 @@ def run_laplace_grid(ev, synth, steps=20000, n=512):
     return rows
 
 
+def run_coexistence(ev, synth, n=256, chunk=100000, window=1000000, max_steps=6000000, tol=1e-5):
+    """Flat-interface coexistence (the paper's Fig. 1) at the scheme's steady
+    state: FP64 D2Q9 slabs of n x 4 cells between n/4 and 3n/4, every case on
+    its own lattice and stream so that the small launches overlap.  A case
+    stops when, over the last `window` steps, its bulk temperature difference
+    moved by less than tol T_c and its bulk densities by less than tol
+    (relative), or at max_steps.  Bulk regions: liquid |x - n/2| < n/16,
+    vapour within n/16 of x = 0.  Cases: the van der Waals fluid of the
+    workloads (RT_c = 0.02) and the same fluid with a halved and quartered
+    (RT_c = 0.01, 0.005: at equal kappa, interfaces sqrt(2) and 2 times
+    wider) at T/Tc = 0.7, 0.8, 0.9, and the Carnahan-Starling fluid at 0.8,
+    0.9.  Each row gives the bulk densities against the equal-area
+    coexistence densities at the mean bulk temperature, and the bulk
+    temperatures."""
+    p = synth.params()
+    spec = [("vdw", s_, tr) for s_ in (1.0, 0.5, 0.25) for tr in (0.7, 0.8, 0.9)] + \
+           [("cs", 1.0, tr) for tr in (0.8, 0.9)]
+    q = n // 16
+    geom = ((n / 2 - q, n / 2 + q), (0, q), (n - q, n))
+    cases = []
+    for eos, a_scale, Tr in spec:
+        pp = dict(synth.params_cs()) if eos == "cs" else dict(p)
+        pp["a"] *= a_scale
+        _, Tc, _ = ev.eos_critical(pp["R"], pp["a"], pp["b"], eos)
+        L = ev.Lattice(2, n, 4, 1, storage="f64")
+        L.set_params(**pp)
+        L.init_slab(Tr, seed=synth.SEED + 1, noise=1e-3)
+        cases.append(dict(eos=eos, pp=pp, Tc=Tc, Tr=Tr, L=L, steps=0, hist=[], done=False))
+    t0 = time.perf_counter()
+    per_window = window // chunk
+    while not all(c["done"] for c in cases):
+        live = [c for c in cases if not c["done"]]
+        for c in live:
+            c["L"].step(chunk)
+        for c in live:
+            c["steps"] += chunk
+            m = c["L"].measure_slab(*geom)
+            c["hist"].append((m[0], m[1], (m[2] - m[3]) / c["Tc"]))
+            if len(c["hist"]) > per_window:
+                a, b = c["hist"][-1 - per_window], c["hist"][-1]
+                steady = (abs(b[2] - a[2]) < tol and abs(b[0] / a[0] - 1) < tol and abs(b[1] / a[1] - 1) < tol)
+                if steady or c["steps"] >= max_steps:
+                    c["done"], c["steady"], c["m"] = True, steady, m
+            if c["steps"] % 1000000 == 0:
+                print(f"{c['eos']} RT_c {c['pp']['R'] * c['Tc']:.4f} T/Tc {c['Tr']}: step {c['steps']}, "
+                      f"rho_l {m[0]:.6f} rho_v {m[1]:.6f} (T_l - T_v)/T_c {(m[2] - m[3]) / c['Tc']:+.6f} "
+                      f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    rows = []
+    for c in cases:
+        m, pp, Tc = c["m"], c["pp"], c["Tc"]
+        Tm = 0.5 * (m[2] + m[3])
+        rl, rv, _ = ev.eos_coexistence(Tm, pp["R"], pp["a"], pp["b"], c["eos"])
+        rows.append({"eos": c["eos"], "RT_c": round(pp["R"] * Tc, 6), "Tr": c["Tr"], "steps": c["steps"],
+                     "steady": c["steady"], "T_liquid_over_Tc": m[2] / Tc, "T_vapour_over_Tc": m[3] / Tc,
+                     "rho_l": m[0], "rho_v": m[1], "rho_l_maxwell": rl, "rho_v_maxwell": rv,
+                     "rho_l_rel": m[0] / rl - 1.0, "rho_v_rel": m[1] / rv - 1.0,
+                     "max_u": c["L"].global_sums()[6]})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        del c["L"]
+    return rows
+
+
+def run_warm_start_scale(ev, synth, horizon=40000):
+    """The learned warm start at production sizes.  Training: the radial
+    profiles of the 16 droplets of the 512^2 grid (R in {20, 30, 40, 60} x
+    T/Tc in {0.7, 0.8, 0.9, 0.95}, 2e4 steps, +-1e-4 noise), 2e4 full-batch
+    Adam iterations at lr 1e-3.  Held out: 512^2 droplets with R in {15, 25,
+    50, 80} x T/Tc in {0.65, 0.75, 0.85, 0.93}, and 128^3 droplets with R in
+    {15, 30, 45} x T/Tc in {0.65, 0.8, 0.95}, each run plain and (when the
+    network is trusted on it) network-seeded with the plain run's mass and
+    energy, for `horizon` steps (warmstart.scale_study); 256^3 droplets of
+    R = 80 at the same three temperatures: the fallback decision only."""
+    from paper_2508_00577_amd import warmstart as W
+    p = synth.params()
+    rho_c, Tc, _ = ev.eos_critical(p["R"], p["a"], p["b"])
+    train = [(R, Tr) for Tr in (0.7, 0.8, 0.9, 0.95) for R in (20.0, 30.0, 40.0, 60.0)]
+    t0 = time.perf_counter()
+    X, Y = W.training_samples(train, (1, 512, 512), p, 20000, rho_c, seed=synth.SEED + 40, noise=1e-4)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, hist = W.train_network(X, Y, synth.xavier_params(), 20000, 1e-3)
+    t_train = time.perf_counter() - t0
+    head = {"train_samples": int(X.shape[0]), "train_runs_s": round(t_data, 1), "train_s": round(t_train, 2),
+            "train_loss": [float(hist[0]), float(hist[-1])], "hull": list(net.hull())}
+    print(json.dumps(head), file=sys.stderr, flush=True)
+    cases = [((1, 512, 512), R, Tr) for R in (15.0, 25.0, 50.0, 80.0) for Tr in (0.65, 0.75, 0.85, 0.93)] + \
+            [((128, 128, 128), R, Tr) for R in (15.0, 30.0, 45.0) for Tr in (0.65, 0.8, 0.95)]
+    rows = []
+    for k, c in enumerate(cases):
+        t0 = time.perf_counter()
+        rec = W.scale_study(net, [c], p, horizon=horizon, check=2000, tol=1e-2, seed=synth.SEED + 60 + k)[0]
+        rec["gpu_host_s"] = round(time.perf_counter() - t0, 1)
+        rows.append(rec)
+        print(json.dumps(rec), file=sys.stderr, flush=True)
+    big = []
+    for Tr in (0.65, 0.8, 0.95):
+        L = ev.Lattice(3, 256, 256, 256, storage="f32")
+        L.set_params(**p)
+        big.append({"shape": [256, 256, 256], "R": 80.0, "Tr": Tr,
+                    "mlp_used": bool(L.init_droplet(80.0, Tr, profile="mlp", mlp=net))})
+        del L
+    head["cases"] = rows + big
+    head["fallbacks"] = int(sum(not r["mlp_used"] for r in rows + big))
+    return head
+
+
 def run_2d(ev, synth, extras, laplace=True):
     """The D2Q9 workloads, results into `extras`: the 512^2 FP32 droplet (with
     `laplace`, continued to 2e4 steps for the spurious currents and the
@@ -199,6 +305,12 @@ def main():
     ap.add_argument("--laplace-grid", action="store_true",
                     help="run the 512^2 static-droplet grid (R x T/Tc, 2e4 steps) and print its Laplace and "
                          "spurious-current figures")
+    ap.add_argument("--coexistence", action="store_true",
+                    help="run FP64 256x4 slabs (three interface resolutions) to their steady state and print "
+                         "their bulk densities and temperatures against the equal-area coexistence densities")
+    ap.add_argument("--warm-start-scale", action="store_true",
+                    help="train the warm-start network on the 512^2 droplet grid and seed held-out 512^2 and 128^3 "
+                         "droplets (4e4 steps each)")
     ap.add_argument("--long-precision", action="store_true",
                     help="compare the 16-bit storages with FP32 after 1e4 steps instead of 1e3")
     args = ap.parse_args()
@@ -224,6 +336,14 @@ def main():
         dt = time.perf_counter() - t0
         print(json.dumps({"workload": "warm-start network training, 1152 samples, 300 Adam iterations",
                           "us_per_iteration": round(dt / 300 * 1e6, 1)}), flush=True)
+        return
+    if args.warm_start_scale:
+        print(json.dumps({"workload": "learned warm start: trained on 512^2 droplets, held-out 512^2 and 128^3 droplets",
+                          **run_warm_start_scale(ev, synth)}), flush=True)
+        return
+    if args.coexistence:
+        print(json.dumps({"workload": "flat interfaces, D2Q9 256x4 periodic slabs, FP64, to the steady state",
+                          "cases": run_coexistence(ev, synth)}), flush=True)
         return
     if args.laplace_grid:
         print(json.dumps({"workload": "2D static droplets, D2Q9 512^2 periodic, FP32, 2e4 steps",

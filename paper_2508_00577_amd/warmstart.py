@@ -99,11 +99,11 @@ def run_to_equilibrium(L, max_steps, check=100, tol=1e-7, rho_c=1.0):
 
 
 def droplet_run(shape, R, Tr, params, steps=None, profile="tanh", mlp=None, storage="f32", max_steps=40000,
-                check=100, tol=1e-7):
+                check=100, tol=1e-7, seed=0, noise=0.0):
     nz, ny, nx = shape
     L = Lattice(3 if nz > 1 else 2, nx, ny, nz, storage=storage)
     L.set_params(**params)
-    used = L.init_droplet(R, Tr, profile=profile, mlp=mlp)
+    used = L.init_droplet(R, Tr, profile=profile, mlp=mlp, seed=seed, noise=noise)
     if steps is not None:
         L.step(steps)
         return L, used, steps, None
@@ -112,13 +112,13 @@ def droplet_run(shape, R, Tr, params, steps=None, profile="tanh", mlp=None, stor
     return L, used, n, conv
 
 
-def training_samples(cases, shape, params, steps, rho_c):
+def training_samples(cases, shape, params, steps, rho_c, seed=0, noise=0.0):
     """(X, Y) from the radial profiles of solver runs: cases = [(R, Tr), ...]."""
     X, Y = [], []
     nz, ny, nx = shape
     centre = ((nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0)
-    for R, Tr in cases:
-        L, _, _, _ = droplet_run(shape, R, Tr, params, steps=steps)
+    for k, (R, Tr) in enumerate(cases):
+        L, _, _, _ = droplet_run(shape, R, Tr, params, steps=steps, seed=seed + k if noise else 0, noise=noise)
         rho, _, _ = L.moments()
         r, prof = radial_profile(rho, centre, R)
         X.append(np.stack([np.full(r.size, Tr), np.full(r.size, R), r / R], 1))
@@ -193,5 +193,81 @@ def warm_start_study(net, cases, shape, params, horizon=40000, check=500, tol=2e
             rec["err0_" + prof] = d[0][1]
             rec["steps_" + prof] = next((n for n, e in d if e < tol), None)
             rec["err_end_" + prof] = d[-1][1]
+        out.append(rec)
+    return out
+
+
+def _trajectory(L, horizon, check, window=100):
+    """Step L to `horizon` and return its density at every `check` steps
+    (FP32 host copies, step 0 first) and, at each check, the drift rate
+    max |rho_n - rho_(n - window)| / window."""
+    rho = L.moments()[0]
+    snaps, drift = [(0, rho.astype(np.float32))], []
+    n = 0
+    while n < horizon:
+        L.step(check - window)
+        a = L.moments()[0]
+        L.step(window)
+        n += check
+        b = L.moments()[0]
+        drift.append((n, float(np.abs(b - a).max() / window)))
+        snaps.append((n, b.astype(np.float32)))
+    return snaps, drift
+
+
+def scale_study(net, cases, params, horizon=40000, check=2000, tol=1e-2, drift_tol=1e-7, seed=0, noise=1e-4):
+    """The warm start at production sizes.  For each (shape, R, Tr) the plain
+    run (tanh profile) and, when the network's profile passes the fallback
+    checks, the network run with the plain run's mass and total energy
+    (evlbm_init_droplet_matched), both with the same seeded noise, run for
+    `horizon` steps with FP32 storage.  Reported per case:
+      - mlp_used: False when the case falls back to the tanh profile (then
+        the network run is the plain run);
+      - steps_eq_plain, steps_eq_mlp: the first check at which the density
+        drift rate over 100 steps is below drift_tol rho_c (None: not within
+        the horizon);
+      - steps_tol_plain, steps_tol_mlp: the first check within `tol` of the
+        plain run's state at the horizon (aligned_difference);
+      - err0_plain, err0_mlp: the distance from that state at step 0;
+        err_end_mlp: at the horizon (the final density error of the network
+        run against the plain run).
+    A 3D case evaluates the network (trained on 2D profiles) on the 3D radius."""
+    rho_c = eos_critical(params["R"], params["a"], params["b"], params.get("eos", "vdw"))[0]
+    out = []
+    for k, (shape, R, Tr) in enumerate(cases):
+        nz, ny, nx = shape
+        D = 3 if nz > 1 else 2
+        rec = dict(shape=list(shape), R=R, Tr=Tr, horizon=horizon, tol=tol)
+        L = Lattice(D, nx, ny, nz, storage="f32")
+        L.set_params(**params)
+        rec["mlp_used"] = bool(L.init_droplet(R, Tr, profile="mlp", mlp=net, seed=seed + k, noise=noise))
+        del L
+        L = Lattice(D, nx, ny, nz, storage="f32")
+        L.set_params(**params)
+        L.init_droplet(R, Tr, profile="tanh", seed=seed + k, noise=noise)
+        target = L.global_sums()
+        snaps, drift = _trajectory(L, horizon, check)
+        del L
+        ref = snaps[-1][1].astype(np.float64)
+        d = [(n, aligned_difference(ref, r.astype(np.float64))) for n, r in snaps]
+        rec["steps_eq_plain"] = next((n for n, v in drift if v < drift_tol * rho_c), None)
+        rec["steps_tol_plain"] = next((n for n, e in d if e < tol), None)
+        rec["err0_plain"] = d[0][1]
+        rec["drift_end_plain"] = drift[-1][1] / rho_c
+        if rec["mlp_used"]:
+            L = Lattice(D, nx, ny, nz, storage="f32")
+            L.set_params(**params)
+            _, T = L.init_droplet_matched(R, Tr, target[0], target[5], profile="mlp", mlp=net,
+                                          seed=seed + k, noise=noise)
+            rec["T_matched_over_T0"] = T / (Tr * eos_critical(params["R"], params["a"], params["b"],
+                                                               params.get("eos", "vdw"))[1])
+            snaps_m, drift_m = _trajectory(L, horizon, check)
+            del L
+            dm = [(n, aligned_difference(ref, r.astype(np.float64))) for n, r in snaps_m]
+            rec["steps_eq_mlp"] = next((n for n, v in drift_m if v < drift_tol * rho_c), None)
+            rec["steps_tol_mlp"] = next((n for n, e in dm if e < tol), None)
+            rec["err0_mlp"] = dm[0][1]
+            rec["err_end_mlp"] = dm[-1][1]
+            rec["drift_end_mlp"] = drift_m[-1][1] / rho_c
         out.append(rec)
     return out
