@@ -179,7 +179,7 @@ def run_coexistence(ev, synth, n=256, chunk=100000, window=1000000, max_steps=60
             c["hist"].append((m[0], m[1], (m[2] - m[3]) / c["Tc"]))
             if len(c["hist"]) > per_window:
                 a, b = c["hist"][-1 - per_window], c["hist"][-1]
-                steady = (abs(b[2] - a[2]) < tol and abs(b[0] / a[0] - 1) < tol and abs(b[1] / a[1] - 1) < tol)
+                steady = bool(abs(b[2] - a[2]) < tol and abs(b[0] / a[0] - 1) < tol and abs(b[1] / a[1] - 1) < tol)
                 if steady or c["steps"] >= max_steps:
                     c["done"], c["steady"], c["m"] = True, steady, m
             if c["steps"] % 1000000 == 0:
@@ -194,8 +194,8 @@ def run_coexistence(ev, synth, n=256, chunk=100000, window=1000000, max_steps=60
         rows.append({"eos": c["eos"], "RT_c": round(pp["R"] * Tc, 6), "Tr": c["Tr"], "steps": c["steps"],
                      "steady": c["steady"], "T_liquid_over_Tc": m[2] / Tc, "T_vapour_over_Tc": m[3] / Tc,
                      "rho_l": m[0], "rho_v": m[1], "rho_l_maxwell": rl, "rho_v_maxwell": rv,
-                     "rho_l_rel": m[0] / rl - 1.0, "rho_v_rel": m[1] / rv - 1.0,
-                     "max_u": c["L"].global_sums()[6]})
+                     "rho_l_rel": float(m[0] / rl - 1.0), "rho_v_rel": float(m[1] / rv - 1.0),
+                     "max_u": float(c["L"].global_sums()[6])})
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
         del c["L"]
     return rows

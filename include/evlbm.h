@@ -331,8 +331,10 @@ int evlbm_mlp_train(evlbm_mlp_t m, const float *X, const float *Y, int n, int it
  * r_hi}.  Errors: EINVAL (null handle, lo > hi). */
 int evlbm_mlp_set_hull(evlbm_mlp_t m, double tr_lo, double tr_hi, double r_lo, double r_hi);
 int evlbm_mlp_get_hull(evlbm_mlp_t m, double out[4]);
-/* Device FP64 density field rho_c * y(T/Tc, R, |x - c|/R) of a lattice of
- * nx*ny*nz cells (nz = 1: 2D distance), enqueued on the network's stream. */
+/* Device FP64 density field rho_c * y(T/Tc, R, min(|x - c|/R, 3)) of a
+ * lattice of nx*ny*nz cells (nz = 1: 2D distance), enqueued on the network's
+ * stream.  Beyond r/R = 3, the radial range of the training profiles (r/R in
+ * [0, 3]) and of evlbm_init_droplet's checks, the field keeps its value at 3. */
 int evlbm_mlp_density_field(evlbm_mlp_t m, int nx, int ny, int nz, double cx, double cy, double cz, double R,
                             double Tr, double rho_c, double *rho_dev);
 

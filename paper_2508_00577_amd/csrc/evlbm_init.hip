@@ -99,16 +99,20 @@ int droplet_fields(evlbm_t h, double cx, double cy, double cz, double R, double 
     const double Tc = cp[1], rho_c = cp[0], rl = co[0], rv = co[1];
     bool mlp_ok = false;
     double hull[4];
-    if (profile == EVLBM_PROFILE_MLP && evlbm_mlp_get_hull(mlp, hull) == EVLBM_OK && Tr >= hull[0] &&
-        Tr <= hull[1] && R >= hull[2] && R <= hull[3]) {
-        // radial probe r/R in [0, 3]: finite, non-increasing (to 1e-3 rho_c) and
+    // the network takes (and its box holds) FP32 inputs: compare in FP32, so
+    // that T/Tc = 0.95 lies inside a box trained up to 0.95f
+    const double trf = (float)Tr, rf = (float)R;
+    if (profile == EVLBM_PROFILE_MLP && evlbm_mlp_get_hull(mlp, hull) == EVLBM_OK && trf >= hull[0] &&
+        trf <= hull[1] && rf >= hull[2] && rf <= hull[3]) {
+        // radial probe r/R in [0, MLP_RMAX] (the field takes the value at
+        // MLP_RMAX beyond it): finite, non-increasing (to 1e-3 rho_c) and
         // within [0.5 rho_v, 1.2 rho_l]
         const int np = 256;
         std::vector<float> X(3 * np), Y(np);
         for (int k = 0; k < np; ++k) {
             X[3 * k] = (float)Tr;
             X[3 * k + 1] = (float)R;
-            X[3 * k + 2] = 3.0f * k / (np - 1);
+            X[3 * k + 2] = MLP_RMAX * k / (np - 1);
         }
         rc = evlbm_mlp_forward(mlp, X.data(), Y.data(), np);
         if (rc) return rc;

@@ -54,6 +54,9 @@ int scan_nonfinite(evlbm_lattice *h);
 int rereference(evlbm_lattice *h);
 size_t store_bytes(int storage);
 hipStream_t mlp_stream(evlbm_mlp_t m);  // the stream a network's kernels run on
+// largest r/R the network's density field evaluates it at (the radial range
+// of its training profiles and of the droplet initialiser's probe)
+constexpr float MLP_RMAX = 3.0f;
 // the wall step and its readouts (evlbm_walls.hip)
 void wall_step(evlbm_lattice *h);
 void wall_analyse(evlbm_lattice *h);

@@ -254,7 +254,10 @@ __global__ void __launch_bounds__(64) k_sum_loss(const float *__restrict__ Lpart
     out[0] = s / (float)n;
 }
 
-// Density field of a droplet from the network: rho(x) = rho_c y(T/Tc, R, |x - c|/R).
+// Density field of a droplet from the network: rho(x) = rho_c y(T/Tc, R,
+// min(|x - c|/R, MLP_RMAX)): beyond r/R = MLP_RMAX, the radial range of the
+// training profiles and of the initialiser's probe, the network is not
+// evaluated and the far field keeps its value there.
 __global__ void __launch_bounds__(64) k_mlp_field(const float *__restrict__ P, int nx, int ny, int nz, double cx,
                                                   double cy, double cz, float R, float Tr, double rho_c,
                                                   double *__restrict__ rho, long n)
@@ -269,7 +272,7 @@ __global__ void __launch_bounds__(64) k_mlp_field(const float *__restrict__ P, i
         if (c < n) {
             const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((long)nx * ny));
             const double dx = x - cx, dy = y - cy, dz = nz > 1 ? z - cz : 0.0;
-            rr = (float)(sqrt(dx * dx + dy * dy + dz * dz) / R);
+            rr = fminf((float)(sqrt(dx * dx + dy * dy + dz * dz) / R), MLP_RMAX);
         }
         xs[3 * l] = Tr;
         xs[3 * l + 1] = R;

@@ -37,11 +37,14 @@ def test_forward_matches_oracle(n):
 
 
 @pytest.mark.parametrize("shape,centre,R,Tr", [((1, 37, 53), (26.0, 18.0, 0.0), 12.5, 0.8),
-                                               ((13, 11, 29), (14.3, 5.0, 6.7), 4.0, 0.7)])
+                                               ((13, 11, 29), (14.3, 5.0, 6.7), 4.0, 0.7),
+                                               ((1, 96, 128), (63.5, 47.5, 0.0), 9.0, 0.85)])
 def test_density_field_matches_oracle(shape, centre, R, Tr):
     """evlbm_mlp_density_field (the network evaluated at every cell, MFMA
     layers) against the FP64 oracle network at the same inputs
-    (T/Tc, R, r/R), r/R rounded to FP32 as the kernel takes it."""
+    (T/Tc, R, min(r/R, 3)), r/R rounded to FP32 as the kernel takes it; the
+    last two grids reach r/R = 4 and 8, where the field keeps its value at
+    r/R = 3 (the radial range of the training profiles)."""
     p = _params(9)
     net = ev.MLP(p)
     rho_c = 1.25
@@ -49,7 +52,7 @@ def test_density_field_matches_oracle(shape, centre, R, Tr):
     nz, ny, nx = shape
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     d2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2 + ((z - centre[2]) ** 2 if nz > 1 else 0.0)
-    rr = (np.sqrt(d2) / R).astype(np.float32).astype(np.float64)
+    rr = np.minimum((np.sqrt(d2) / R).astype(np.float32), np.float32(3.0)).astype(np.float64)
     X = np.stack([np.full(rr.size, np.float32(Tr)), np.full(rr.size, np.float32(R)), rr.ravel()], 1)
     want = rho_c * OM.forward(p, X).reshape(shape)
     err = np.abs(got - want).max() / rho_c
@@ -127,6 +130,12 @@ def test_learned_warm_start_reduces_steps():
     assert r["mlp_used"]
     assert r["err0_mlp_matched"] < r["err0_tanh"] / 3
     assert r["steps_mlp_matched"] is not None and r["steps_mlp_matched"] < r["steps_tanh"]
+    # the trained box's edge (T/Tc = 0.88, held as FP32) is inside it for the
+    # same value given in FP64 (R = 14: a training radius whose profiles reach
+    # r/R = 3)
+    L = ev.Lattice(2, shape[2], shape[1], 1, storage="f32")
+    L.set_params(**params)
+    assert L.init_droplet(14.0, 0.88, profile="mlp", mlp=net)
 
 
 def test_network_is_trusted_only_on_its_training_box():
