@@ -245,6 +245,50 @@ def run_warm_start_scale(ev, synth, horizon=40000):
     return head
 
 
+def run_next_rows(ev, synth, extras, n=256, steps=200):
+    """Throughput of the widened rows.  On the benchmark's 3D lattice (n^3
+    D3Q27, FP32, droplet R = 40 n/256 at T/Tc = 0.8, +-1e-4 noise): the
+    Carnahan-Starling closure (one-pass step, the closure compiled into the
+    collision) and Prandtl number 2 (two-pass step: moment pass and the
+    collision with the quasi-equilibrium term), each with its kernels timed by
+    HIP events (evlbm_profile_step) and the collision's algorithmic GB/s
+    (4 Q s bytes per cell).  And the supersonic Couette channel between
+    diffuse walls (D2Q9, 128 cells, FP64; four launches per step, replayed
+    from graphs): steps per second."""
+    import torch
+    cells = n ** 3
+    alg = 4 * 27 * 4 * cells
+    R = 40.0 * n / 256
+    for name, pp in (("cs", synth.params_cs()), ("prandtl2", dict(synth.params(), Pr=2.0))):
+        L = ev.Lattice(3, n, n, n, storage="f32")
+        L.set_params(**pp)
+        L.init_droplet(R, 0.8, seed=synth.SEED + 2, noise=1e-4)
+        L.step(32)
+        t = timed_steps(L, steps)
+        t_other, t_col = L.profile_step(20)
+        extras[f"{name}_f32_MLUPS"] = round(cells * steps / t / 1e6, 1)
+        extras[f"{name}_collide_ms"] = round(t_col, 4)
+        extras[f"{name}_other_kernel_ms"] = round(t_other, 4)
+        extras[f"{name}_collide_frac_of_hbm_peak"] = round(alg / (t_col * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        del L
+        torch.cuda.empty_cache()
+    import oracle.couette as C
+    p = synth.params()
+    nx, Tw = 128, 1.5 * synth.T_CRIT
+    U = C.wall_speed_for_mach(float(nx), 1.0, Tw, 1.2, p["a"], p["b"], p["tau"])
+    L = ev.Lattice(2, nx, 1, 1, storage="f64")
+    L.set_params(**dict(p, kappa=0.0))
+    L.set_walls(Tw, U)
+    L.init_fields(np.ones((1, 1, nx)), np.full((1, 1, nx), Tw))
+    L.step(1024)
+    L.synchronize()
+    t0 = time.perf_counter()
+    L.step(32768)
+    L.synchronize()
+    extras["couette_d2q9_128_f64_steps_per_s"] = round(32768 / (time.perf_counter() - t0), 1)
+    del L
+
+
 def run_2d(ev, synth, extras, laplace=True):
     """The D2Q9 workloads, results into `extras`: the 512^2 FP32 droplet (with
     `laplace`, continued to 2e4 steps for the spurious currents and the
@@ -311,6 +355,9 @@ def main():
     ap.add_argument("--warm-start-scale", action="store_true",
                     help="train the warm-start network on the 512^2 droplet grid and seed held-out 512^2 and 128^3 "
                          "droplets (4e4 steps each)")
+    ap.add_argument("--only-next", action="store_true",
+                    help="time only the widened rows (Carnahan-Starling closure and Prandtl number 2 on the 3D "
+                         "lattice, the Couette channel), e.g. under a profiler")
     ap.add_argument("--long-precision", action="store_true",
                     help="compare the 16-bit storages with FP32 after 1e4 steps instead of 1e3")
     args = ap.parse_args()
@@ -336,6 +383,12 @@ def main():
         dt = time.perf_counter() - t0
         print(json.dumps({"workload": "warm-start network training, 1152 samples, 300 Adam iterations",
                           "us_per_iteration": round(dt / 300 * 1e6, 1)}), flush=True)
+        return
+    if args.only_next:
+        extras = {}
+        run_next_rows(ev, synth, extras, n=args.n)
+        print(json.dumps({"workload": "widened rows: Carnahan-Starling and Prandtl-number steps on the 3D droplet, "
+                                      "Couette channel", **extras}), flush=True)
         return
     if args.warm_start_scale:
         print(json.dumps({"workload": "learned warm start: trained on 512^2 droplets, held-out 512^2 and 128^3 droplets",
@@ -410,6 +463,7 @@ def main():
 
     if not args.no_extras:
         extras = {}
+        run_next_rows(ev, synth, extras, n=n)
         run_2d(ev, synth, extras)
         # mixed precision: 16-bit deviation storage against FP32 on the same 3D
         # workload (density error after `cmp` steps; the full 1e4-step horizon
