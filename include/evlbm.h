@@ -71,7 +71,7 @@ enum {
                                   library's): g relaxes with tau_g = tau/Pr in both terms of eq. pre_LBM and keeps
                                   f's relaxation for its viscous-heating flux u . Pi^neq (Pi^neq = sum c c
                                   (fh - f^eq)) through a zero-mass, zero-energy term on the axis directions; then
-                                  k = (5/2) R mu/Pr.  Pr != 1 takes the two-pass D3Q27 step. */
+                                  k = (5/2) R mu/Pr. */
     EVLBM_OPT_PUSH_MOMENTS = 7 /* 1 = one-pass step (default), 0 = two-pass step, where the moments are pulled
                                   again before each collision.  D3Q27 with FP32 or FP64 storage: the collision
                                   pushes the next moments (16-bit D3Q27 storage is always two-pass).  D2Q9:

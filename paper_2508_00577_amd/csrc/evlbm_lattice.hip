@@ -118,16 +118,25 @@ struct Ops {
         }
         if constexpr (PUSH) {
             // the one-pass step, the benchmark's kernel: the pressure closure
-            // is compiled in rather than branched on per cell
-            if (buf && h->eos == EVLBM_EOS_VDW)
+            // is compiled in rather than branched on per cell, and so is the
+            // quasi-equilibrium term of Pr != 1 (250 VGPRs with it, still two
+            // waves per SIMD in FP32)
+            const bool vpr = h->prandtl != 1.0;
+            if (buf && h->eos == EVLBM_EOS_VDW && !vpr)
                 hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true, true, false, EVLBM_EOS_VDW>), g, b, 0, h->stream,
                                    (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
-            else if (buf)
+            else if (buf && !vpr)
                 hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true, true, false, EVLBM_EOS_CS>), g, b, 0, h->stream,
                                    (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
-            else
+            else if (buf)
+                hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, true, true, true>), g, b, 0, h->stream,
+                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
+            else if (!vpr)
                 hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, false, true>), g, b, 0, h->stream, (const T *)src,
                                    (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
+            else
+                hipLaunchKernelGGL((k_collide_zm<S, TX, TY, ZC, false, true, true>), g, b, 0, h->stream,
+                                   (const T *)src, (T *)dst, (const R *)h->m, make_params<R>(h), nbx, nby, mn, sh);
             return;
         }
         if (buf)
@@ -390,7 +399,7 @@ int scan_nonfinite(evlbm_lattice *h)
 // Does the step push the next moments (D3Q27 one-pass step)?
 static bool pushes(const evlbm_lattice *h)
 {
-    return h->D == 3 && h->push && h->shell != nullptr && !h->walls && h->prandtl == 1.0;
+    return h->D == 3 && h->push && h->shell != nullptr && !h->walls;
 }
 // the one-pass D2Q9 step: the collision sums its halo's moments itself
 static bool fused(const evlbm_lattice *h) { return h->D == 2 && h->push && !h->walls; }

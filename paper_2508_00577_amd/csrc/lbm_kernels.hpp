@@ -1222,13 +1222,11 @@ __global__ void __launch_bounds__(TX *TY)
             qp[1] = p.lambda * (P0 * ring_grad<1, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[1] * Phip);
             qp[2] = p.lambda * (P0 * ring_grad<2, R>(fm[FTD], f0[FTD], fp[FTD], c1, ZT::R1X) + u[2] * Phip);
             if constexpr (PUSH) {
-                // the one-pass step runs at Pr = 1 only (the host takes the
-                // two-pass step otherwise): no quasi-equilibrium pre-pass
                 auto push_sink = [&](int i, R f, R g) {
                     vf[i] = f;
                     vg[i] = g;
                 };
-                collide_pulled<D, S, Pops, decltype(push_sink), false>(fr, gr, pops, p, po, rho, inv_rho, K, ez.Z,
+                collide_pulled<D, S, Pops, decltype(push_sink), VPR>(fr, gr, pops, p, po, rho, inv_rho, K, ez.Z,
                                                                        theta, u, F, Phi, qp, push_sink);
             } else
                 collide_pulled<D, S, Pops, NoSink, VPR>(fr, gr, pops, p, po, rho, inv_rho, K, ez.Z, theta, u, F, Phi,

@@ -1,6 +1,7 @@
 """The Prandtl-number option (EVLBM_OPT_PRANDTL) through the C ABI against the
 oracle's reading of the quasi-equilibrium relaxation of g: the D2Q9 step,
-the D3Q27 two-pass step (which Pr != 1 takes) and the walls, then the
+the D3Q27 one-pass step (the two-pass step is checked against it in
+test_gpu_push.py) and the walls, then the
 subsonic Couette temperature rise Pr U_w^2/(20 R)."""
 import numpy as np
 import pytest

@@ -28,10 +28,10 @@ def _state(shape, noise=1e-3, seed=synth.SEED + 11):
     return synth.droplet(shape, R, rl, rv, noise=noise, seed=seed), np.full(shape, T0)
 
 
-def _lattice(shape, storage, push, rho, T, graph=True):
+def _lattice(shape, storage, push, rho, T, graph=True, Pr=1.0):
     nz, ny, nx = shape
     L = ev.Lattice(3, nx, ny, nz, storage=storage)
-    L.set_params(**P)
+    L.set_params(**P, Pr=Pr)
     L.set_option(ev.OPT_PUSH_MOMENTS, 1 if push else 0)
     L.set_option(ev.OPT_USE_GRAPH, 1 if graph else 0)
     L.init_fields(rho, T)
@@ -60,6 +60,24 @@ def test_one_pass_matches_two_pass_f64(shape):
     print(f"  e_f={ef:.2e} e_g={eg:.2e} e_rho={e[0]:.2e} e_u={e[1]:.2e} e_T={e[2]:.2e}", flush=True)
     assert ef < 1e-12 and eg < 1e-12
     assert max(e) < 1e-12
+
+
+@pytest.mark.parametrize("Pr", [0.5, 2.0])
+@pytest.mark.parametrize("shape", [(13, 11, 37), (70, 12, 20), (2, 5, 6)])
+def test_one_pass_matches_two_pass_prandtl_f64(shape, Pr):
+    """The one-pass step with the quasi-equilibrium term (Pr != 1) against
+    the two-pass step: populations within 1e-12 after 25 steps."""
+    rho, T = _state(shape)
+    a = _lattice(shape, "f64", True, rho, T, Pr=Pr)
+    b = _lattice(shape, "f64", False, rho, T, Pr=Pr)
+    a.step(25)
+    b.step(25)
+    fa, ga = a.get_populations()
+    fb, gb = b.get_populations()
+    ef = np.abs(fa - fb).max() / np.abs(fb).max()
+    eg = np.abs(ga - gb).max() / np.abs(gb).max()
+    print(f"one-pass vs two-pass Pr {Pr} f64 {shape}: e_f={ef:.2e} e_g={eg:.2e}", flush=True)
+    assert ef < 1e-12 and eg < 1e-12
 
 
 @pytest.mark.parametrize("storage,tol", [("f64", 1e-14), ("f32", 2e-6)])
