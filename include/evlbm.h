@@ -268,8 +268,9 @@ int evlbm_batch_destroy(evlbm_batch_t b);
 int evlbm_batch_set_params(evlbm_batch_t b, double R, double a, double bexcl, double kappa, double tau,
                            double lambda, double sphi);
 
-/* Batch options: EVLBM_OPT_SPHI, EVLBM_OPT_REREF_EVERY and EVLBM_OPT_EOS, as on
- * a lattice, shared by every domain (EVLBM_OPT_PRANDTL accepts only 1).  Errors: EINVAL (other keys, bad values). */
+/* Batch options: EVLBM_OPT_SPHI, EVLBM_OPT_REREF_EVERY, EVLBM_OPT_EOS and
+ * EVLBM_OPT_PRANDTL, as on a lattice, shared by every domain.  Errors: EINVAL
+ * (other keys, bad values). */
 int evlbm_batch_set_option(evlbm_batch_t b, int key, double value);
 
 /* Initialise domain k from host FP64 fields rho[N_k], u[2 N_k] (nullable), T[N_k].

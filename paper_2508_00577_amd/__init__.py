@@ -366,9 +366,10 @@ class Batch:
             _lib.evlbm_batch_destroy(h)
             self._h = None
 
-    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0, eos="vdw"):
+    def set_params(self, R=1.0, a=0.0, b=0.0, kappa=0.0, tau=1.0, lam=1.0, sphi=-1.0, eos="vdw", Pr=1.0):
         _check(lib().evlbm_batch_set_params(self._h, R, a, b, kappa, tau, lam, sphi))
         _check(lib().evlbm_batch_set_option(self._h, OPT_EOS, float(EOS[eos])))
+        _check(lib().evlbm_batch_set_option(self._h, OPT_PRANDTL, float(Pr)))
 
     def init_domain(self, k, rho, T, u=None):
         nx, ny = self.sizes[k]

@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(BX *BY)
     }
 }
 
-template <int S, int BX, int BY>
+template <int S, int BX, int BY, bool VPR = false>
 __global__ void __launch_bounds__(BX *BY)
     k_batch_collide(const StoreT<S> *__restrict__ src, StoreT<S> *__restrict__ dst, const RealT<S> *__restrict__ m,
                     const DomainRec *__restrict__ dom, const int4 *__restrict__ tiles, int ntiles,
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(BX *BY)
         const int4 tl = tiles[t];
         const DomainRec d = dom[tl.x];
         const StepParams<RealT<S>> q = domain_params(p, d);
-        collide_block<2, S, BX, BY, 1, true>(src + d.pop_off, dst + d.pop_off, m + d.m_off, q, tl.y, tl.z, 0);
+        collide_block<2, S, BX, BY, 1, true, VPR>(src + d.pop_off, dst + d.pop_off, m + d.m_off, q, tl.y, tl.z, 0);
         __syncthreads();  // the next tile reuses the LDS staging buffers
     }
 }
@@ -98,7 +98,7 @@ struct evlbm_batch {
     DomainRec *d_dom = nullptr;
     int4 *d_tiles[NVARIANT] = {nullptr, nullptr, nullptr, nullptr};
     int ntiles[NVARIANT] = {0, 0, 0, 0};
-    int grid[NVARIANT][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // persistent grid: moments, collide
+    int grid[NVARIANT][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // persistent grid: moments, collide (Pr = 1, Pr != 1)
     int variant = 0;
     double R = 1.0, a = 0.0, b = 0.0, kappa = 0.0, tau = 1.0, lambda = 1.0, sphi = -1.0;
     int eos = EVLBM_EOS_VDW;
@@ -170,17 +170,25 @@ struct BOps {
     }
     static void collide(evlbm_batch *b, const void *src, void *dst)
     {
-        hipLaunchKernelGGL((k_batch_collide<S, BX, BY>), dim3(b->grid[V][1]), dim3(BX, BY), 0, b->stream,
-                           (const T *)src, (T *)dst, (const R *)b->m, b->d_dom, b->d_tiles[V], b->ntiles[V],
-                           bparams<R>(b));
+        // Prandtl number != 1: the collision with the quasi-equilibrium term
+        if (b->prandtl != 1.0)
+            hipLaunchKernelGGL((k_batch_collide<S, BX, BY, true>), dim3(b->grid[V][2]), dim3(BX, BY), 0, b->stream,
+                               (const T *)src, (T *)dst, (const R *)b->m, b->d_dom, b->d_tiles[V], b->ntiles[V],
+                               bparams<R>(b));
+        else
+            hipLaunchKernelGGL((k_batch_collide<S, BX, BY>), dim3(b->grid[V][1]), dim3(BX, BY), 0, b->stream,
+                               (const T *)src, (T *)dst, (const R *)b->m, b->d_dom, b->d_tiles[V], b->ntiles[V],
+                               bparams<R>(b));
     }
     static void occupancy(evlbm_batch *b, int cus)
     {
-        int nm = 0, nc = 0;
+        int nm = 0, nc = 0, nv = 0;
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nm, k_batch_moments<S, BX, BY>, BX * BY, 0);
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nc, k_batch_collide<S, BX, BY>, BX * BY, 0);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nv, k_batch_collide<S, BX, BY, true>, BX * BY, 0);
         b->grid[V][0] = std::max(1, std::min(b->ntiles[V], cus * std::max(nm, 1)));
         b->grid[V][1] = std::max(1, std::min(b->ntiles[V], cus * std::max(nc, 1)));
+        b->grid[V][2] = std::max(1, std::min(b->ntiles[V], cus * std::max(nv, 1)));
     }
 };
 
@@ -418,7 +426,8 @@ int evlbm_batch_set_option(evlbm_batch_t b, int key, double value)
         b->eos = (int)value;
         break;
     case EVLBM_OPT_PRANDTL:
-        if (value != 1.0) return fail(EVLBM_EINVAL, "the batch runs at Prandtl number 1 (set Pr on a lattice)");
+        if (!(value > 0) || !std::isfinite(value)) return fail(EVLBM_EINVAL, "the Prandtl number must be positive");
+        b->prandtl = value;
         break;
     default:
         return fail(EVLBM_EINVAL, "option %d is not a batch option", key);

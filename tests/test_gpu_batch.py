@@ -196,3 +196,37 @@ def test_batch_autotune_restores_state(tmp_path):
     assert again["variant"] == entry["variant"]
     b.step(33)  # graph + eager remainder after the tuned shape is set
     assert np.isfinite(b.moments(0)[0]).all()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_batch_prandtl_domain_equals_single_lattice_and_oracle(storage):
+    """Prandtl number 2 in the batch (the collision with the quasi-equilibrium
+    term): every domain bit for bit as the same domain stepped alone on a
+    lattice with the same tile shape, and in FP64 the first two domains within
+    1e-12 of the oracle after 60 steps."""
+    b = ev.Batch([(nx, ny) for _, nx, ny, _ in DOMS], storage=storage)
+    b.set_params(**P, Pr=2.0)
+    b.set_tile(1)
+    fields = []
+    for k, (kind, nx, ny, Tr) in enumerate(DOMS):
+        rho, T = _fields(kind, nx, ny, Tr, synth.SEED * 1000 + 70 + k)
+        b.init_domain(k, rho, T)
+        fields.append((rho, T))
+    b.step(60)
+    for k, (kind, nx, ny, Tr) in enumerate(DOMS):
+        L = ev.Lattice(2, nx, ny, 1, storage=storage)
+        L.set_params(**P, Pr=2.0)
+        L.init_fields(*fields[k])
+        L.step(60)
+        fa, ga = b.get_populations(k)
+        fb, gb = L.get_populations()
+        assert np.array_equal(fa, fb) and np.array_equal(ga, gb), f"domain {k}"
+        if storage == "f64" and k < 2:
+            o = oracle.Lattice(2, nx, ny, 1)
+            o.set_params(**P, Pr=2.0)
+            o.init(*fields[k])
+            o.step(60)
+            fo, go = o.get_pops()
+            e = max(np.abs(fa - fo).max() / np.abs(fo).max(), np.abs(ga - go).max() / np.abs(go).max())
+            print(f"Pr 2 batch domain {k} vs oracle: {e:.2e}", flush=True)
+            assert e < 1e-12
