@@ -358,6 +358,9 @@ def main():
     ap.add_argument("--only-next", action="store_true",
                     help="time only the widened rows (Carnahan-Starling closure and Prandtl number 2 on the 3D "
                          "lattice, the Couette channel), e.g. under a profiler")
+    ap.add_argument("--only-16bit", action="store_true",
+                    help="time only the FP16-deviation storage on the 3D workload (two-pass step), e.g. under a "
+                         "profiler")
     ap.add_argument("--long-precision", action="store_true",
                     help="compare the 16-bit storages with FP32 after 1e4 steps instead of 1e3")
     args = ap.parse_args()
@@ -383,6 +386,19 @@ def main():
         dt = time.perf_counter() - t0
         print(json.dumps({"workload": "warm-start network training, 1152 samples, 300 Adam iterations",
                           "us_per_iteration": round(dt / 300 * 1e6, 1)}), flush=True)
+        return
+    if args.only_16bit:
+        n = args.n
+        L = make_droplet(ev, synth, (n, n, n), 40.0 * n / 256, 0.8, "f16dev")
+        L.step(32)
+        t = timed_steps(L, 200)
+        t_mom, t_col = L.profile_step(20)
+        cells = n ** 3
+        print(json.dumps({"workload": f"3D droplet, D3Q27 {n}^3, FP16 deviation storage (two-pass step)",
+                          "MLUPS": round(cells * 200 / t / 1e6, 1), "collide_ms": round(t_col, 4),
+                          "moments_ms": round(t_mom, 4),
+                          "collide_frac_of_hbm_peak": round(4 * 27 * 2 * cells / (t_col * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}),
+              flush=True)
         return
     if args.only_next:
         extras = {}
