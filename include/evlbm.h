@@ -26,6 +26,7 @@
 #ifndef EVLBM_H
 #define EVLBM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -205,6 +206,25 @@ int evlbm_profile_step(evlbm_t h, int nsteps, double out[2]);
 
 /* Wait for all work enqueued on the handle's stream. */
 int evlbm_synchronize(evlbm_t h);
+
+/* Size of one population buffer (A or B) in bytes, and its direction stride
+ * in elements: a buffer holds 2Q direction arrays (f then g, velocity index i
+ * = (cx+1) + 3(cy+1) + 9(cz+1)) of N cells each, x fastest, consecutive
+ * arrays `stride` elements apart (N plus a pad that keeps the arrays off
+ * each other's HBM channels), elements of the storage's type (8, 4 or 2
+ * bytes; 16-bit storage holds scaled deviations from the per-cell reference
+ * state).  stride is nullable.  Errors: EINVAL (null handle or bytes). */
+int evlbm_population_bytes(evlbm_t h, size_t *bytes, long *stride);
+
+/* Let the lattice keep its populations in caller-owned device memory (e.g.
+ * two torch tensors): a and b (distinct, non-overlapping, 256-byte aligned,
+ * at least evlbm_population_bytes bytes each, on the lattice's device)
+ * replace the library's two buffers.  The current state is copied into them
+ * (the call blocks on the handle's stream), the library's own buffers are
+ * freed, and captured step graphs are rebuilt.  The caller keeps a and b
+ * alive until evlbm_destroy, which does not free them.  Errors: EINVAL
+ * (null, too small, misaligned, overlapping or non-device buffers), EHIP. */
+int evlbm_attach_buffers(evlbm_t h, void *a, void *b, size_t bytes);
 
 /* Diffuse walls normal to x for the thermal Couette flow (the paragraph after
  * eq. P0E, Fig. 2): a wall at rest half a cell before the first cell

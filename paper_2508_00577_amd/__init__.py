@@ -68,6 +68,8 @@ def lib():
         L.evlbm_checkpoint_save.argtypes = [_vp, ctypes.c_char_p]
         L.evlbm_checkpoint_load.argtypes = [_vp, ctypes.c_char_p]
         L.evlbm_synchronize.argtypes = [_vp]
+        L.evlbm_population_bytes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_long)]
+        L.evlbm_attach_buffers.argtypes = [_vp, _vp, _vp, ctypes.c_size_t]
         L.evlbm_profile_step.argtypes = [_vp, ctypes.c_int, _dp]
         L.evlbm_eos_coexistence.argtypes = [ctypes.c_int] + [ctypes.c_double] * 4 + [_dp]
         L.evlbm_eos_critical.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3 + [_dp]
@@ -227,6 +229,24 @@ class Lattice:
 
     def synchronize(self):
         _check(lib().evlbm_synchronize(self._h))
+
+    def population_bytes(self):
+        """(bytes of one population buffer, direction stride in elements)."""
+        nb, st = ctypes.c_size_t(), ctypes.c_long()
+        _check(lib().evlbm_population_bytes(self._h, ctypes.byref(nb), ctypes.byref(st)))
+        return nb.value, st.value
+
+    def attach_buffers(self, a, b):
+        """Keep the populations in two caller-owned device tensors (each at
+        least population_bytes()[0] bytes); the lattice holds references to
+        them so they outlive it."""
+        nbytes = min(a.numel() * a.element_size(), b.numel() * b.element_size())
+        _check(lib().evlbm_attach_buffers(self._h, _vp(a.data_ptr()), _vp(b.data_ptr()), nbytes))
+        # torch's allocator must not hand the memory out again while the
+        # lattice's stream may still use it
+        a.record_stream(self.stream)
+        b.record_stream(self.stream)
+        self._attached = (a, b)
 
     def profile_step(self, nsteps=20):
         """Average kernel durations (ms) of (moments, collide) over nsteps real steps."""

@@ -13,6 +13,7 @@ struct evlbm_lattice {
     int device = 0;
     hipStream_t stream = nullptr;
     void *buf[2] = {nullptr, nullptr};  // population buffers, f then g: 2Q arrays of N cells, ds apart
+    bool own_buf = true;                // false once the caller attached its own population buffers
     int cur = 0;                        // buffer holding the current state
     void *m = nullptr;                  // pulled moments rho, j (D), e: [(D+2)][N] of the current state
     void *m_alt = nullptr;              // D3Q27 one-pass step: the next state's moments (swapped with m)

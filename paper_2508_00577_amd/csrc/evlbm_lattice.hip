@@ -565,7 +565,7 @@ int evlbm_destroy(evlbm_t h)
     for (int k = 0; k < 2; ++k)
         if (h->graph_exec_par[k]) hipGraphExecDestroy(h->graph_exec_par[k]);
     for (int k = 0; k < 2; ++k)
-        if (h->buf[k]) hipFree(h->buf[k]);
+        if (h->buf[k] && h->own_buf) hipFree(h->buf[k]);
     if (h->m) hipFree(h->m);
     if (h->m_alt) hipFree(h->m_alt);
     if (h->shell) hipFree(h->shell);
@@ -1143,6 +1143,47 @@ int evlbm_profile_step(evlbm_t h, int nsteps, double out[2])
     if (e != hipSuccess) return hip_fail(e, "profiling the step kernels");
     out[0] = tm / nsteps;
     out[1] = tc / nsteps;
+    return EVLBM_OK;
+}
+
+int evlbm_population_bytes(evlbm_t h, size_t *bytes, long *stride)
+{
+    if (!h || !bytes) return fail(EVLBM_EINVAL, "null argument");
+    *bytes = (size_t)h->ds * 2 * h->Q * store_bytes(h->storage);
+    if (stride) *stride = h->ds;
+    return EVLBM_OK;
+}
+
+int evlbm_attach_buffers(evlbm_t h, void *a, void *b, size_t bytes)
+{
+    if (!h || !a || !b) return fail(EVLBM_EINVAL, "null argument");
+    size_t need = 0;
+    evlbm_population_bytes(h, &need, nullptr);
+    if (bytes < need) return fail(EVLBM_EINVAL, "population buffers of %zu bytes, need %zu", bytes, need);
+    if (a == b) return fail(EVLBM_EINVAL, "the two population buffers must differ");
+    if (((uintptr_t)a | (uintptr_t)b) % 256 != 0) return fail(EVLBM_EINVAL, "population buffers must be 256-byte aligned");
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    if (pa < pb + need && pb < pa + need) return fail(EVLBM_EINVAL, "the two population buffers overlap");
+    hipPointerAttribute_t at;
+    for (void *ptr : {a, b}) {
+        if (hipPointerGetAttributes(&at, ptr) != hipSuccess || at.type != hipMemoryTypeDevice || at.device != h->device)
+            return fail(EVLBM_EINVAL, "population buffers must be device memory of the lattice's device");
+    }
+    (void)hipGetLastError();
+    // the state moves with the buffers: copy both (the current one and the
+    // other, which the next step overwrites) on the lattice's stream
+    hipError_t e = hipMemcpyAsync(a, h->buf[0], need, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b, h->buf[1], need, hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "attach population buffers");
+    if (h->own_buf) {
+        (void)hipFree(h->buf[0]);
+        (void)hipFree(h->buf[1]);
+    }
+    h->buf[0] = a;
+    h->buf[1] = b;
+    h->own_buf = false;
+    invalidate_graph(h);
     return EVLBM_OK;
 }
 

@@ -366,3 +366,39 @@ def test_long_run_mass_is_conserved(storage):
     drift = abs(f.sum() - m0) / m0
     print(f"{storage}: relative stored-mass drift after 1e5 steps {drift:.2e}", flush=True)
     assert drift < (1e-9 if storage == "f32" else 1e-6)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_attached_buffers_are_used_and_change_nothing(storage):
+    """evlbm_attach_buffers: after 10 steps the populations move into two
+    torch tensors; 40 more steps (graph-replayed) give bit for bit the state of
+    a lattice that kept its own buffers, and the tensors hold that state (the
+    first direction array of the current buffer is f_0 as stored); a buffer
+    too small is refused."""
+    import torch
+    shape = (9, 11, 37)
+    rho, T = _state("droplet", shape, 0.8, 1e-4)
+    runs = []
+    for attach in (False, True):
+        L = ev.Lattice(3, shape[2], shape[1], shape[0], storage=storage)
+        L.set_params(**P)
+        L.init_fields(rho, T)
+        L.step(10)
+        if attach:
+            nbytes, stride = L.population_bytes()
+            a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            L.attach_buffers(a, b)
+        L.step(40)
+        runs.append(L.get_populations())
+        if attach:
+            L.synchronize()
+            if storage == "f32":
+                N = shape[0] * shape[1] * shape[2]
+                cur = a if L.step_count % 2 == 0 else b
+                f0 = cur.view(torch.float32)[:N].double().cpu().numpy().reshape(shape)
+                assert np.array_equal(f0, runs[-1][0][0]), "the attached buffer holds the state"
+            with pytest.raises(ev.EvlbmError):
+                L.attach_buffers(a[: nbytes // 2], b)
+    (fa, ga), (fb, gb) = runs
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
