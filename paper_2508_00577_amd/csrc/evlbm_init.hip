@@ -209,7 +209,7 @@ int evlbm_init_droplet_matched(evlbm_t h, double cx, double cy, double cz, doubl
     bool used = false;
     double s[8], T1 = 0.0;
     rc = droplet_fields(h, cx, cy, cz, R, Tr, profile, mlp, width, seed, noise, d, d + N, &used);
-    double cp[3], co[3];
+    double cp[3] = {0.0, 0.0, 0.0}, co[3] = {0.0, 0.0, 0.0};
     if (rc == EVLBM_OK) rc = coexistence_at(h, Tr, cp, co);
     const double T0 = Tr * cp[1];
     // the stored mass of the profile, then the profile scaled to `mass`

@@ -417,9 +417,16 @@ extern "C" int evlbm_set_walls(evlbm_t h, int enable, double T_wall, double U_wa
 {
     using namespace evlbm;
     if (!h) return fail(EVLBM_EINVAL, "null handle");
+    auto drop_graphs = [h] {
+        for (int k = 0; k < 2; ++k) {
+            if (h->graph_exec_par[k]) (void)hipGraphExecDestroy(h->graph_exec_par[k]);
+            h->graph_exec_par[k] = nullptr;
+        }
+    };
     if (!enable) {
         h->walls = false;
         h->m_valid = false;
+        drop_graphs();  // the captured steps launch the wall kernels
         return EVLBM_OK;
     }
     if (h->storage != EVLBM_F64 && h->storage != EVLBM_F32)
@@ -427,18 +434,20 @@ extern "C" int evlbm_set_walls(evlbm_t h, int enable, double T_wall, double U_wa
     if (h->nx < 2 || !(T_wall > 0) || !std::isfinite(U_wall))
         return fail(EVLBM_EINVAL, "walls need nx >= 2, T_wall > 0 and a finite wall speed");
     const size_t rb = real_bytes(h->storage);
-    if (!h->wall_fh) {
-        hipError_t e = hipMalloc(&h->wall_fh, rb * 2 * h->Q * h->N);
+    if (!h->wall_fh || !h->wall_fld) {
+        hipError_t e = h->wall_fh ? hipSuccess : hipMalloc(&h->wall_fh, rb * 2 * h->Q * h->N);
         if (e == hipSuccess) e = hipMalloc(&h->wall_fld, rb * (3 * h->D + 2) * h->N);
-        if (e != hipSuccess) return fail(EVLBM_ENOMEM, "wall work buffers: %s", hipGetErrorString(e));
+        if (e != hipSuccess) {
+            (void)hipFree(h->wall_fh);
+            h->wall_fh = nullptr;
+            h->wall_fld = nullptr;
+            return fail(EVLBM_ENOMEM, "wall work buffers: %s", hipGetErrorString(e));
+        }
     }
     h->walls = true;
     h->Tw = T_wall;
     h->Uw = U_wall;
     h->m_valid = false;
-    for (int k = 0; k < 2; ++k) {
-        if (h->graph_exec_par[k]) (void)hipGraphExecDestroy(h->graph_exec_par[k]);
-        h->graph_exec_par[k] = nullptr;
-    }
+    drop_graphs();
     return EVLBM_OK;
 }

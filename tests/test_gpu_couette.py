@@ -81,3 +81,30 @@ def test_supersonic_couette_steady_state():
     assert e_T < 3e-3 and e_rho < 6e-3 and e_u < 8e-3
     assert Ma == pytest.approx(an["Mach"][-1], abs=0.015)
     assert abs(g.global_sums()[0] / m0 - 1) < 1e-12
+
+
+def test_walls_switched_off_restore_the_periodic_step():
+    """A lattice that ran 32 graph-replayed steps with walls and then switched
+    them off continues exactly as a periodic lattice given the same
+    populations (the captured wall steps are dropped with the walls)."""
+    nz, ny, nx = 1, 5, 40
+    Tw = 1.5 * synth.T_CRIT
+    x = np.arange(nx)
+    rho = np.broadcast_to(1.0 + 0.1 * np.cos(2 * np.pi * x / nx), (nz, ny, nx)).copy()
+    T = np.full((nz, ny, nx), Tw)
+    a = ev.Lattice(2, nx, ny, nz, storage="f64")
+    a.set_params(**_params())
+    a.set_walls(Tw, 0.2)
+    a.init_fields(rho, T)
+    a.step(32)
+    f, g = a.get_populations()
+    a.set_walls(Tw, 0.2, enable=False)
+    a.step(32)
+    b = ev.Lattice(2, nx, ny, nz, storage="f64")
+    b.set_params(**_params())
+    b.init_fields(rho, T)
+    b.set_populations(f, g)
+    b.step(32)
+    fa, ga = a.get_populations()
+    fb, gb = b.get_populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
