@@ -8,6 +8,8 @@ eq. LB_energy_balance), independence of lambda (comment (ii) after
 eq. viscosity), the van der Waals adiabatic sound speed, and Maxwell's
 equal-area coexistence (Fig. 1).
 """
+import math
+
 import numpy as np
 import pytest
 from scipy.optimize import curve_fit
@@ -359,3 +361,32 @@ def test_windowed_step_equals_full_step(D, shape):
     for k, (x, y, z) in enumerate(cells):
         np.testing.assert_allclose(sf[k], f1[:, z, y, x], rtol=1e-14, atol=1e-15)
         np.testing.assert_allclose(sg[k], g1[:, z, y, x], rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("D,u0", [(2, (0.0, 0.0, 0.0)), (2, (0.02, -0.015, 0.0)), (3, (0.0, 0.0, 0.0)),
+                                   (3, (0.02, -0.015, 0.01))])
+def test_positivity_and_speed_diagnostics_on_uniform_states(D, u0):
+    """The last two global sums, max |u| and the smallest streamed population
+    (the positivity diagnostic), on uniform states where both have closed
+    forms.  The equilibrium of eq. feq is rho prod_a psi(c_a; u_a, theta +
+    u_a^2) with psi(0) = 1 - theta - u_a^2 and psi(+-1) = (theta + u_a^2 +-
+    u_a)/2 (eq. phi).  With |u_a| < theta + u_a^2 < 2/3 on every axis all
+    factors are positive and the factor against the flow, (theta + u_a^2 -
+    |u_a|)/2, is the smallest of the three, so the smallest member is the
+    direction against the flow on every axis:
+    rho prod_a (theta + u_a^2 - |u_a|)/2 over the D axes; max |u| is |u0|.
+    (theta = RT/(1 - b rho) for the van der Waals closure: 0.0318 here.)"""
+    shape = (1, 6, 7) if D == 2 else (5, 4, 6)
+    rho0, RT0 = 1.3, 0.9 * synth.T_CRIT
+    L = _lattice(D, shape)
+    u = np.zeros((D,) + shape)
+    for a in range(D):
+        u[a] = u0[a]
+    L.init(np.full(shape, rho0), np.full(shape, RT0), u)
+    s = L.global_sums()
+    theta = RT0 / (1.0 - P["b"] * rho0)
+    fmin = rho0
+    for a in range(D):
+        fmin *= 0.5 * (theta + u0[a] ** 2 - abs(u0[a]))
+    assert s[7] == pytest.approx(fmin, rel=1e-13)
+    assert s[6] == pytest.approx(math.sqrt(sum(v * v for v in u0[:D])), rel=1e-13, abs=1e-15)
