@@ -151,6 +151,9 @@ def test_flat_interface_converges_to_maxwell_with_resolution():
         for L, _ in Ls:
             L.step(100000)
     for L, pp in Ls:
+        # a flat interface carries no spurious current at the steady state
+        # (measured max |u| 7e-7 at 2e6 steps)
+        assert L.global_sums()[6] < 1e-5
         m = L.measure_slab((n / 2 - q, n / 2 + q), (0, q), (n - q, n))
         _, Tc, _ = TH.critical_point(pp["R"], pp["a"], pp["b"])
         rl, rv, _ = TH.coexistence(0.5 * (m[2] + m[3]), pp["R"], pp["a"], pp["b"])
