@@ -108,3 +108,30 @@ def test_walls_switched_off_restore_the_periodic_step():
     fa, ga = a.get_populations()
     fb, gb = b.get_populations()
     assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+
+
+def test_supersonic_couette_converges_at_first_order():
+    """The supersonic Couette flow's deviation from the continuum profile is
+    the slip velocity and temperature jump of diffuse walls, first order in
+    the cell size over the channel width: doubling the channel from 64 to
+    128 cells (Mach 1.2 at the moving wall, steady states after 1e5 and 4e5
+    steps) halves the density, temperature and velocity errors (ratios
+    within 1.6-2.4; the oracle's 64- and 128-cell channels give 2.1, 2.0,
+    2.0)."""
+    Tw, tau = 1.5 * synth.T_CRIT, 1.0
+    errs = []
+    for nx, steps in ((64, 100000), (128, 400000)):
+        U = C.wall_speed_for_mach(float(nx), 1.0, Tw, 1.2, A, B, tau)
+        an = C.at(C.profile(float(nx), 1.0, Tw, U, A, B, tau), np.arange(nx) + 0.5)
+        g = ev.Lattice(2, nx, 1, 1, storage="f64")
+        g.set_params(**_params(tau))
+        g.set_walls(Tw, U)
+        g.init_fields(np.ones((1, 1, nx)), np.full((1, 1, nx), Tw))
+        g.step(steps)
+        r, u, T = g.moments()
+        errs.append((np.abs(r[0, 0] - an["rho"]).max() / an["rho"].max(),
+                     np.abs(T[0, 0] - an["T"]).max() / an["T"].max(),
+                     np.abs(u[1, 0, 0] - an["u"]).max() / U))
+    ratios = [a / b for a, b in zip(*errs)]
+    print(f"Couette 64 -> 128: errors {errs[0]} -> {errs[1]}, ratios {ratios}", flush=True)
+    assert all(1.6 < q < 2.4 for q in ratios)
