@@ -106,12 +106,13 @@ def test_2d_tiles_in_xcd_order_f64():
 
 
 def test_c1_flat_interface_f64_1000_steps():
-    """128 x 32 flat interface, T/Tc = 0.9, FP64: moments after 1, 100 and 1000 steps."""
+    """128 x 32 flat interface, T/Tc = 0.9, FP64: moments after 1, 100, 1000
+    and 2000 steps (the flat-interface workload's horizon)."""
     shape = (1, 32, 128)
     rho, T = _state("slab", shape, 0.9, 1e-3)
     g, o = _pair(2, shape, "f64", rho, T)
     _compare(g, o, 1e-12, "c1 f64 step 0")
-    for n, tol in ((1, 1e-12), (99, 1e-11), (900, 1e-10)):
+    for n, tol in ((1, 1e-12), (99, 1e-11), (900, 1e-10), (1000, 1e-10)):
         g.step(n)
         o.step(n)
         _compare(g, o, tol, f"c1 f64 step {g.step_count}")
