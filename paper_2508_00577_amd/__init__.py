@@ -4,8 +4,8 @@ Argument marshalling only: every step of the method runs in the library's HIP
 kernels.  PyTorch provides device memory (output tensors) and streams.  The
 names follow include/evlbm.h; errors raise EvlbmError with the library's
 message.  The library must have been built (``python -m
-paper_2508_00577_amd.build`` or ``__graft_entry__.build()``); nothing here
-falls back to another implementation.
+paper_2508_00577_amd.build``); nothing here falls back to another
+implementation.
 """
 from __future__ import annotations
 
