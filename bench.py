@@ -307,30 +307,39 @@ def run_2d(ev, synth, extras, laplace=True):
             "max_u": s2[6], "dp": md[4] - md[5], "R_e": md[6], "dp_times_R_e": (md[4] - md[5]) * md[6],
             "T_liquid_over_Tc": md[2] / synth.T_CRIT, "T_vapour_over_Tc": md[3] / synth.T_CRIT}
     del L2
-    # batched sweep: 64 uneven D2Q9 domains (64^2 .. 512^2), T/Tc in [0.65, 0.97], FP32
+    # the same lattice with FP16 deviation storage (half the bytes per cell)
+    L2 = make_droplet(ev, synth, (1, 512, 512), 40.0, 0.8, "f16dev")
+    L2.step(64)
+    t = timed_steps(L2, 2048, sums_every=1024)
+    extras["d2q9_512sq_f16dev_MLUPS"] = round(512 * 512 * 2048 / t / 1e6, 1)
+    del L2
+    # batched sweep: 64 uneven D2Q9 domains (64^2 .. 512^2), T/Tc in [0.65, 0.97],
+    # FP32, then the same sweep with FP16 deviation storage
     table = synth.batch_table()
-    B = ev.Batch([(d["nx"], d["ny"]) for d in table], storage="f32")
-    B.set_params(**synth.params())
-    for k, d in enumerate(table):
-        T0 = d["Tr"] * synth.T_CRIT
-        rl, rv, _ = ev.eos_coexistence(T0, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
-        shp = (1, d["ny"], d["nx"])
-        rho = (synth.slab(shp, rl, rv, noise=1e-3, seed=d["seed"]) if d["kind"] == "slab" else
-               synth.droplet(shp, d["R"], rl, rv, noise=1e-4, seed=d["seed"]))
-        B.init_domain(k, rho, np.full(shp, T0))
-    tune = B.autotune(steps=10)
-    B.step(64)
-    B.synchronize()
-    t0 = time.perf_counter()
-    B.step(512)
-    B.synchronize()
-    tb = time.perf_counter() - t0
-    info = B.info()
-    extras["batch64_MLUPS"] = round(info["cells"] * 512 / tb / 1e6, 1)
-    extras["batch64_cells"] = info["cells"]
-    extras["batch64_tile"] = list(info["tile"])
-    extras["batch64_autotune_ms_per_step"] = [round(x, 4) for x in tune["ms_per_step"]]
-    del B
+    for storage, key in (("f32", "batch64"), ("f16dev", "batch64_f16dev")):
+        B = ev.Batch([(d["nx"], d["ny"]) for d in table], storage=storage)
+        B.set_params(**synth.params())
+        for k, d in enumerate(table):
+            T0 = d["Tr"] * synth.T_CRIT
+            rl, rv, _ = ev.eos_coexistence(T0, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
+            shp = (1, d["ny"], d["nx"])
+            rho = (synth.slab(shp, rl, rv, noise=1e-3, seed=d["seed"]) if d["kind"] == "slab" else
+                   synth.droplet(shp, d["R"], rl, rv, noise=1e-4, seed=d["seed"]))
+            B.init_domain(k, rho, np.full(shp, T0))
+        tune = B.autotune(steps=10)
+        B.step(64)
+        B.synchronize()
+        t0 = time.perf_counter()
+        B.step(512)
+        B.synchronize()
+        tb = time.perf_counter() - t0
+        info = B.info()
+        extras[f"{key}_MLUPS"] = round(info["cells"] * 512 / tb / 1e6, 1)
+        extras[f"{key}_tile"] = list(info["tile"])
+        extras[f"{key}_autotune_ms_per_step"] = [round(x, 4) for x in tune["ms_per_step"]]
+        if storage == "f32":
+            extras["batch64_cells"] = info["cells"]
+        del B
 
 
 def main():
