@@ -227,6 +227,40 @@ def test_errors_are_reported():
     assert e.value.name == "ENONFINITE"
 
 
+@pytest.mark.parametrize("call,why", [
+    (lambda L: L.set_option(ev.OPT_EOS, 7), "unknown pressure closure"),
+    (lambda L: L.set_option(ev.OPT_PRANDTL, 0.0), "Prandtl number <= 0"),
+    (lambda L: L.set_option(ev.OPT_PRANDTL, float("inf")), "Prandtl number not finite"),
+    (lambda L: L.set_walls(0.0, 0.1), "wall temperature <= 0"),
+    (lambda L: L.set_walls(0.03, float("nan")), "wall speed not finite"),
+    (lambda L: L.init_slab(1.2), "no two phases above T_c"),
+    (lambda L: L.init_slab(0.8, noise=1.0), "noise >= 1"),
+    (lambda L: L.init_droplet(-3.0, 0.8), "negative radius"),
+    (lambda L: L.init_droplet(5.0, 0.8, profile="mlp"), "network profile without a network"),
+    (lambda L: L.init_droplet_matched(5.0, 0.8, -1.0, 1.0, profile="tanh"), "non-positive target mass"),
+])
+def test_widened_calls_reject_bad_arguments(call, why):
+    """The calls added with the pressure closures, the Prandtl option, the
+    walls and the initialisers refuse bad arguments with EINVAL (or EINVAL's
+    physical sibling ENONPHYS) and leave the lattice usable."""
+    L = ev.Lattice(2, 24, 16, 1, storage="f32")
+    L.set_params(**P)
+    with pytest.raises(ev.EvlbmError) as e:
+        call(L)
+    assert e.value.name in ("EINVAL", "ENONPHYS"), why
+    L.init_slab(0.8)
+    L.step(2)
+    assert np.isfinite(L.global_sums()).all()
+
+
+def test_walls_refuse_16bit_storage():
+    L = ev.Lattice(2, 24, 1, 1, storage="f16dev")
+    L.set_params(**P)
+    with pytest.raises(ev.EvlbmError) as e:
+        L.set_walls(0.03, 0.1)
+    assert e.value.name == "EINVAL"
+
+
 def test_graph_replay_matches_eager():
     """Chunks replayed from captured graphs give the same bits as eager launches."""
     shape = (1, 40, 96)
