@@ -381,8 +381,9 @@ int evlbm_init_slab(evlbm_t h, double x0, double x1, double Tr, double width, ui
 /* Droplet of radius R centred at (cx, cy, cz) at T/Tc = Tr, at rest:
  * TANH = (rho_l + rho_v)/2 - (rho_l - rho_v)/2 tanh((r - R)/width); MLP = the
  * network's profile, falling back to TANH when (Tr, R) lies outside the
- * network's trusted box (evlbm_mlp_set_hull) or the radial profile is
- * non-finite, increasing in r or outside [0.5 rho_v, 1.2 rho_l].
+ * network's trusted box (evlbm_mlp_set_hull; compared in FP32, the network's
+ * input precision) or the radial profile on r/R in [0, 3] is non-finite,
+ * increasing in r or outside [0.5 rho_v, 1.2 rho_l].
  * *used_mlp (nullable) tells which was used. */
 int evlbm_init_droplet(evlbm_t h, double cx, double cy, double cz, double R, double Tr, int profile, evlbm_mlp_t mlp,
                        double width, uint64_t seed, double noise, int *used_mlp);
