@@ -1091,6 +1091,18 @@ __global__ void __launch_bounds__(TX *TY)
                     s_edge[side][ty][e][0] = side ? vf[ip] : vf[im];
                     s_edge[side][ty][e][1] = side ? vg[ip] : vg[im];
                 }
+            // a one-column tile's lane is both end lanes: its c_x = +1
+            // values leave the row on the right as well
+            if (W == 1) {
+#pragma unroll
+                for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+                    for (int cy = -1; cy <= 1; ++cy) {
+                        const int ip = 3 * (cy + 1) + 9 * (cz + 1) + 2, e = 3 * (cy + 1) + (cz + 1);
+                        s_edge[1][ty][e][0] = vf[ip];
+                        s_edge[1][ty][e][1] = vg[ip];
+                    }
+            }
         }
         if constexpr (!SPREAD) {
             if (ty == ty_bot && tx < W) ring_commit(k, tx, -1, rc_dn);
