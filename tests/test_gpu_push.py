@@ -80,12 +80,13 @@ def test_one_pass_matches_two_pass_prandtl_f64(shape, Pr):
     assert ef < 1e-12 and eg < 1e-12
 
 
-@pytest.mark.parametrize("shape", [(5, 6, 65), (3, 4, 1), (1, 1, 1), (4, 9, 129), (13, 11, 37)])
+@pytest.mark.parametrize("shape", [(5, 6, 65), (3, 4, 1), (1, 1, 1), (4, 9, 129), (13, 11, 37), (41, 5, 70)])
 def test_one_pass_matches_two_pass_f32(shape):
     """FP32 storage (the 64-wide tile, one row per wave), including lattices
     whose last tile is one column wide (nx = 1, 65, 129), where one lane is
-    both end lanes of its row: the collision arithmetic is the same in both
-    steps and the moments differ in summation order only."""
+    both end lanes of its row, and a one-plane last z-chunk (nz = 41): the
+    collision arithmetic is the same in both steps and the moments differ in
+    summation order only."""
     rho, T = _state(shape)
     print(f"one-pass vs two-pass f32 {shape}", flush=True)
     a = _lattice(shape, "f32", True, rho, T)
