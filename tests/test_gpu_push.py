@@ -80,17 +80,19 @@ def test_one_pass_matches_two_pass_prandtl_f64(shape, Pr):
     assert ef < 1e-12 and eg < 1e-12
 
 
+@pytest.mark.parametrize("Pr", [1.0, 2.0])
 @pytest.mark.parametrize("shape", [(5, 6, 65), (3, 4, 1), (1, 1, 1), (4, 9, 129), (13, 11, 37), (41, 5, 70)])
-def test_one_pass_matches_two_pass_f32(shape):
+def test_one_pass_matches_two_pass_f32(shape, Pr):
     """FP32 storage (the 64-wide tile, one row per wave), including lattices
     whose last tile is one column wide (nx = 1, 65, 129), where one lane is
     both end lanes of its row, and a one-plane last z-chunk (nz = 41): the
     collision arithmetic is the same in both steps and the moments differ in
-    summation order only."""
+    summation order only.  Pr = 2 runs the kernels with the quasi-equilibrium
+    term."""
     rho, T = _state(shape)
-    print(f"one-pass vs two-pass f32 {shape}", flush=True)
-    a = _lattice(shape, "f32", True, rho, T)
-    b = _lattice(shape, "f32", False, rho, T)
+    print(f"one-pass vs two-pass f32 {shape} Pr {Pr}", flush=True)
+    a = _lattice(shape, "f32", True, rho, T, Pr=Pr)
+    b = _lattice(shape, "f32", False, rho, T, Pr=Pr)
     a.step(25)
     b.step(25)
     fa, ga = a.get_populations()
