@@ -119,7 +119,7 @@ struct Ops {
         if constexpr (PUSH) {
             // the one-pass step, the benchmark's kernel: the pressure closure
             // is compiled in rather than branched on per cell, and so is the
-            // quasi-equilibrium term of Pr != 1 (250 VGPRs with it, still two
+            // quasi-equilibrium term of Pr != 1 (251 VGPRs with it, still two
             // waves per SIMD in FP32)
             const bool vpr = h->prandtl != 1.0;
             if (buf && h->eos == EVLBM_EOS_VDW && !vpr)
