@@ -474,6 +474,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     # the counters' bytes over the live launch time: the HBM rate the kernel sustains
+                     "traffic_GBps": None if traffic is None else round(traffic / (t_col * 1e-3) / 1e9, 1),
                      "kernel": "k_collide_zm (one-pass: stream, collide, push next moments)",
                      "kernel_ms": round(t_col, 4), "fixup_kernel": "k_push_fixup",
                      "fixup_kernel_ms": round(t_fix, 4),
