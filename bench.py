@@ -139,6 +139,42 @@ def run_laplace_grid(ev, synth, steps=20000, n=512):
     return rows
 
 
+def run_laplace_3d(ev, synth, n=128, Tr=0.8):
+    """Laplace's law in 3D, dp = 2 sigma / R: FP32 static droplets of R = n/8,
+    3n/16 and n/4 on an n^3 periodic D3Q27 lattice at T/Tc = Tr, seeded
+    +-1e-4 noise, run 3e5 (n/128)^2 steps, long enough for the bulk
+    temperatures to meet (the thermal diffusion time of a 128^3 box is ~5e4
+    steps).  Six times per run: the bulk pressure jump dp, the equimolar
+    radius R_e, dp R_e / 2 (-> sigma), the bulk temperatures and the largest
+    speed, from the library's FP64 measurement (bulk liquid r < R/2, vapour
+    r > R + n/8)."""
+    radii = (n / 8, 3 * n / 16, n / 4)
+    steps = int(300000 * (n / 128) ** 2) // 6 * 6
+    every = steps // 6
+    p = synth.params()
+    T0 = Tr * synth.T_CRIT
+    rl, rv, _ = ev.eos_coexistence(T0, p["R"], p["a"], p["b"])
+    c = (n - 1) / 2
+    rows = []
+    for R in radii:
+        L = ev.Lattice(3, n, n, n, storage="f32")
+        L.set_params(**p)
+        L.init_fields(synth.droplet((n, n, n), R, rl, rv, noise=1e-4, seed=synth.SEED + 300 + int(R)),
+                      np.full((n, n, n), T0))
+        traj = []
+        for k in range(every, steps + 1, every):
+            L.step(every)
+            s = L.global_sums()
+            md = L.measure_droplet((c, c, c), R / 2, R + n / 8)
+            traj.append({"step": k, "dp": md[4] - md[5], "R_e": md[6], "half_dp_R_e": 0.5 * (md[4] - md[5]) * md[6],
+                         "T_liquid_over_Tc": md[2] / synth.T_CRIT, "T_vapour_over_Tc": md[3] / synth.T_CRIT,
+                         "max_u": s[6]})
+            print(json.dumps({"R": R, **traj[-1]}), file=sys.stderr, flush=True)
+        rows.append({"R": R, "Tr": Tr, "n": n, "trajectory": traj})
+        del L
+    return rows
+
+
 def run_coexistence(ev, synth, n=256, chunk=100000, window=1000000, max_steps=6000000, tol=1e-5):
     """Flat-interface coexistence (the paper's Fig. 1) at the scheme's steady
     state: FP64 D2Q9 slabs of n x 4 cells between n/4 and 3n/4, every case on
@@ -358,6 +394,9 @@ def main():
     ap.add_argument("--laplace-grid", action="store_true",
                     help="run the 512^2 static-droplet grid (R x T/Tc, 2e4 steps) and print its Laplace and "
                          "spurious-current figures")
+    ap.add_argument("--laplace-3d", action="store_true",
+                    help="run 128^3 static droplets (R = 16, 24, 32, T/Tc = 0.8, FP32; --n for another size) for "
+                         "3e5 steps and print their Laplace figures (dp R_e / 2 -> sigma) every 5e4 steps")
     ap.add_argument("--coexistence", action="store_true",
                     help="run FP64 256x4 slabs (three interface resolutions) to their steady state and print "
                          "their bulk densities and temperatures against the equal-area coexistence densities")
@@ -422,6 +461,11 @@ def main():
     if args.coexistence:
         print(json.dumps({"workload": "flat interfaces, D2Q9 256x4 periodic slabs, FP64, to the steady state",
                           "cases": run_coexistence(ev, synth)}), flush=True)
+        return
+    if args.laplace_3d:
+        n3 = 128 if args.n == 256 else args.n
+        print(json.dumps({"workload": f"3D static droplets, D3Q27 {n3}^3 periodic, FP32, T/Tc = 0.8",
+                          "cases": run_laplace_3d(ev, synth, n=n3)}), flush=True)
         return
     if args.laplace_grid:
         print(json.dumps({"workload": "2D static droplets, D2Q9 512^2 periodic, FP32, 2e4 steps",
