@@ -375,6 +375,29 @@ def run_2d(ev, synth, extras, laplace=True):
         extras[f"{key}_autotune_ms_per_step"] = [round(x, 4) for x in tune["ms_per_step"]]
         if storage == "f32":
             extras["batch64_cells"] = info["cells"]
+            # per-domain coexistence at 5000 steps (the autotuner restores the
+            # state, so 576 steps are done): each slab domain's bulk densities
+            # (liquid |x - nx/2| < nx/16, vapour within nx/16 of x = 0) against
+            # the equal-area densities at its mean bulk temperature
+            B.step(5000 - 576)
+            rows = []
+            for k, d in enumerate(table):
+                if d["kind"] != "slab":
+                    continue
+                rho, _, T = B.moments(k)
+                nx = d["nx"]
+                x = np.arange(nx)
+                q = nx / 16
+                liq = np.abs(x - nx / 2) < q
+                vap = (x < q) | (x >= nx - q)
+                rl_m, rv_m = rho[0][:, liq].mean(), rho[0][:, vap].mean()
+                Tm = 0.5 * (T[0][:, liq].mean() + T[0][:, vap].mean())
+                rl_e, rv_e, _ = ev.eos_coexistence(Tm, synth.R_GAS, synth.A_ATTR, synth.B_EXCL)
+                rows.append([round(Tm / synth.T_CRIT, 4), round(rl_m / rl_e - 1, 5), round(rv_m / rv_e - 1, 5)])
+            extras["batch64_slab_coexistence_at_5000_steps"] = {
+                "T_over_Tc_drho_l_drho_v": rows,
+                "max_abs_drho_l": max(abs(r[1]) for r in rows),
+                "drho_v_range": [min(r[2] for r in rows), max(r[2] for r in rows)]}
         del B
 
 
