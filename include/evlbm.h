@@ -172,7 +172,7 @@ int evlbm_global_sums_noalloc(evlbm_t h, double *out_dev);
  * out = {rho_in, rho_out, T_in, T_out, P_in, P_out, R_e, cells_in}
  * with P_in, P_out the region means of the cell pressures
  * P = rho R T Z(rho) - a rho^2 of the lattice's pressure closure (van der
- * Waals Z = 1/(1 - b rho), or Carnahan-Starling; evlbm_set_eos) and, for
+ * Waals Z = 1/(1 - b rho), or Carnahan-Starling; EVLBM_OPT_EOS) and, for
  * droplets, the equimolar radius R_e from sum (rho - rho_out)/(rho_in -
  * rho_out) (2D: area, 3D: volume).  Blocks.  Errors: EINVAL, ESTATE, EHIP. */
 int evlbm_measure(evlbm_t h, int kind, const double *geom, double out[8]);
