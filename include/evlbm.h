@@ -50,9 +50,10 @@ enum { EVLBM_D2Q9 = 2, EVLBM_D3Q27 = 3 };
  * h_i(x) = (f_i(x) - f^ref_i(x))/s_i(x) in 16 bits (round to nearest even) and
  * decode to FP32 for the arithmetic: f^ref, g^ref are the equilibria at rest
  * (eq. feq, eq. geq with u = 0) of a per-cell reference state (rho_ref,
- * theta_ref), s = f^ref for f and (3/2) RT_ref f^ref for g.  The reference
- * state is set from the initial fields and, on a lattice, refreshed from the
- * stored state of every cell every EVLBM_OPT_REREF_EVERY steps (default 100).
+ * theta_ref), s = f^ref for f and theta_ref/(1 - theta_ref) f^ref for g.
+ * The reference state is set from the initial fields and, on a lattice,
+ * refreshed from the stored state of every cell every EVLBM_OPT_REREF_EVERY
+ * steps (default 100).
  * F16DEV keeps the density within 1e-3 of FP32 storage and of the FP64 oracle.
  * BF16DEV (8-bit significand) is experimental: it misses that bar in 3D
  * (about 1.3e-3 after 1e4 steps at 128^3, 3e-3 against the oracle after 1000
