@@ -272,10 +272,12 @@ int evlbm_copy_probe(double bytes, int reps, double *gbps_out);
 /* ------------------------------------------------------------------------
  * Batched D2Q9 domains (a sweep over many uneven periodic domains sharing the
  * EOS and relaxation parameters, e.g. a T/Tc sweep).  All domains advance
- * together: each step is one persistent launch of the moment kernel and one
- * of the stencil + collision kernel over the tiles of every domain, replayed
- * from captured hipGraphs.  A domain of the batch evolves bit for bit as the
- * same domain stepped alone as a lattice of the same storage.
+ * together: each step is one persistent launch of the one-pass stencil +
+ * collision kernel over the tiles of every domain (the collision sums its
+ * tile's halo moments from the pulled populations; a moment kernel runs for
+ * readouts only), replayed from captured hipGraphs.  A domain of the batch
+ * evolves bit for bit as the same domain stepped alone as a lattice of the
+ * same storage.
  * ------------------------------------------------------------------------ */
 typedef struct evlbm_batch *evlbm_batch_t;
 typedef struct {
@@ -403,7 +405,8 @@ int evlbm_init_droplet_matched(evlbm_t h, double cx, double cy, double cz, doubl
                                evlbm_mlp_t mlp, double width, uint64_t seed, double noise, double mass,
                                double energy, int *used_mlp, double *T_used);
 
-/* Build information: "gfx950 <storage variants> <date>" (static string). */
+/* Build information: the library, its target, lattices and storages,
+ * "evlbm gfx950 D2Q9/D3Q27 F64/F32/F16DEV/BF16DEV" (static string). */
 const char *evlbm_version(void);
 
 #ifdef __cplusplus
