@@ -62,6 +62,7 @@ def lib():
         L.evlbm_step_count.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
         L.evlbm_read_moments.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int]
         L.evlbm_global_sums.argtypes = [_vp, _dp]
+        L.evlbm_global_sums_noalloc.argtypes = [_vp, _vp]
         L.evlbm_measure.argtypes = [_vp, ctypes.c_int, _dp, _dp]
         L.evlbm_get_populations.argtypes = [_vp, _vp, _vp, ctypes.c_int]
         L.evlbm_set_populations.argtypes = [_vp, _vp, _vp, ctypes.c_int]
@@ -277,6 +278,18 @@ class Lattice:
     def global_sums(self):
         out = np.zeros(8)
         _check(lib().evlbm_global_sums(self._h, out.ctypes.data_as(_dp)))
+        return out
+
+    def global_sums_into(self, out):
+        """The global sums into a caller-owned device tensor of 8 float64
+        values, enqueued on the lattice's stream without any allocation
+        (evlbm_global_sums_noalloc; lattices of at most 2^24 cells)."""
+        import torch
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64 and out.numel() >= 8
+                and out.is_contiguous()):
+            raise ValueError("out must be a contiguous CUDA float64 tensor of at least 8 values")
+        _check(lib().evlbm_global_sums_noalloc(self._h, _vp(out.data_ptr())))
+        out.record_stream(self.stream)
         return out
 
     def measure_slab(self, liquid, vapour1, vapour2):

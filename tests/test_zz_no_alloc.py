@@ -51,3 +51,19 @@ def test_noalloc_sums_reject_oversized_lattice():
     import torch
     out = torch.zeros(8, dtype=torch.float64, device="cuda")
     assert lib.evlbm_global_sums_noalloc(L._h, ctypes.c_void_p(out.data_ptr())) == -1
+
+
+def test_binding_global_sums_into_matches_global_sums():
+    """The binding's Lattice.global_sums_into (the same entry point) fills a
+    caller's device tensor with the values of global_sums, and refuses a
+    tensor it cannot write."""
+    import torch
+    L = _lattice(3, (13, 11, 37), "f32", synth.SEED + 47)
+    ref = L.global_sums()
+    out = torch.full((8,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    L.global_sums_into(out)
+    L.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref)
+    with pytest.raises(ValueError):
+        L.global_sums_into(torch.zeros(8, dtype=torch.float32, device="cuda"))
